@@ -1,0 +1,264 @@
+"""okpz oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain CPU reference of the octahedron-model hot path (Kelling & Odor,
+arXiv:1110.6745): the seeded tiled dynamics of Sec. II, the textbook
+random-sequential judge, height reconstruction (Sec. I) and the exact width
+sums of Eq. (Wdef).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library (``paper_1110_6745_amd``) and never imports it.
+
+Lattice arrays are ``numpy.uint8`` of shape ``(Ly, Lx)``; bit 0 of a byte is
+``bx = [sigma_x = +1]`` and bit 1 is ``by = [sigma_y = +1]`` of that site.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "okpz_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+def build() -> str:
+    """Compile the oracle's C source into ``oracle/liboracle.so``."""
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", _SRC,
+           "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    L = ctypes.CDLL(_LIB_PATH)
+    L.or_philox.argtypes = [_u32p, _u32p, _u32p]
+    L.or_philox.restype = None
+    L.or_threshold.argtypes = [ctypes.c_double]
+    L.or_threshold.restype = ctypes.c_uint64
+    L.or_geometry.argtypes = [ctypes.c_int64, ctypes.c_int64, _i32p, _i32p, _i32p]
+    L.or_geometry.restype = ctypes.c_int
+    L.or_flat.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64]
+    L.or_flat.restype = None
+    L.or_block_sweep.argtypes = [_u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
+                                 ctypes.c_int32, _i64p, _i64p, _i64p, _u8p]
+    L.or_block_sweep.restype = ctypes.c_int
+    L.or_block_shift.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
+                                 ctypes.c_int32, _i32p, _i32p]
+    L.or_block_shift.restype = None
+    L.or_sweep.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                           ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _i64p,
+                           _i64p, _i64p, ctypes.c_int]
+    L.or_sweep.restype = ctypes.c_int
+    L.or_rsu_sweep.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                               ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _i64p,
+                               _i64p, _i64p]
+    L.or_rsu_sweep.restype = None
+    L.or_heights.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _i64p]
+    L.or_heights.restype = None
+    L.or_width.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _i64p,
+                           _i64p]
+    L.or_width.restype = ctypes.c_int
+    L.or_ensemble.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_uint64, ctypes.c_int64,
+                              ctypes.c_int64, ctypes.c_int, _i64p]
+    L.or_ensemble.restype = ctypes.c_int
+    L.or_num_threads.argtypes = []
+    L.or_num_threads.restype = ctypes.c_int
+    L.or_set_num_threads.argtypes = [ctypes.c_int]
+    L.or_set_num_threads.restype = None
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray, t):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(t)
+
+
+def _check_lattice(lat: np.ndarray) -> None:
+    if lat.dtype != np.uint8 or lat.ndim != 2 or not lat.flags["C_CONTIGUOUS"]:
+        raise TypeError("lattice must be a C-contiguous uint8 array of shape (Ly, Lx)")
+
+
+# --------------------------------------------------------------------------
+# Random numbers and constants of the dynamics
+# --------------------------------------------------------------------------
+def philox(counter, key) -> tuple:
+    """Philox4x32-10 of a 4-word counter under a 2-word key (Salmon et al.)."""
+    c = np.asarray(counter, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    o = np.zeros(4, dtype=np.uint32)
+    lib().or_philox(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(o, _u32p))
+    return tuple(int(v) for v in o)
+
+
+def threshold(prob: float) -> int:
+    """Integer acceptance threshold T with accept iff draw < T (Eq. (1))."""
+    return int(lib().or_threshold(float(prob)))
+
+
+def geometry(Lx: int, Ly: int) -> tuple:
+    """(Bx, By, C): block sides and thread-cell side of the decomposition."""
+    bx, by, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    if lib().or_geometry(Lx, Ly, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(c)) != 0:
+        raise ValueError(f"unsupported lattice {Lx}x{Ly}")
+    return bx.value, by.value, c.value
+
+
+def block_shift(seed: int, s: int, Bx: int, By: int) -> tuple:
+    sx, sy = ctypes.c_int32(), ctypes.c_int32()
+    lib().or_block_shift(seed, s, Bx, By, ctypes.byref(sx), ctypes.byref(sy))
+    return sx.value, sy.value
+
+
+# --------------------------------------------------------------------------
+# Lattice states and dynamics
+# --------------------------------------------------------------------------
+def flat(Lx: int, Ly: int) -> np.ndarray:
+    """Flat zig-zag initial state (Sec. III); its height at (0,0) is 0."""
+    lat = np.empty((Ly, Lx), dtype=np.uint8)
+    lib().or_flat(_ptr(lat, _u8p), Lx, Ly)
+    return lat
+
+
+class Counts:
+    """Accepted attachments and detachments of a run."""
+
+    def __init__(self):
+        self.att = 0
+        self.det = 0
+
+
+def sweep(lat: np.ndarray, p: float, q: float, seed: int, s: int, H0: int,
+          check: bool = False, counts: Counts | None = None) -> int:
+    """One MCS (sweep index ``s``) of the tiled dynamics, in place.
+
+    Returns the new absolute height of site (0,0).  ``check`` turns on the
+    bond-conflict checker (raises if any bond is touched twice in one step).
+    """
+    _check_lattice(lat)
+    Ly, Lx = lat.shape
+    h = ctypes.c_int64(H0)
+    a, d = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = lib().or_sweep(_ptr(lat, _u8p), Lx, Ly, threshold(p), threshold(q), seed, s,
+                        ctypes.byref(h), ctypes.byref(a), ctypes.byref(d), int(check))
+    if rc == -1:
+        raise AssertionError("bond conflict inside one step of the tiled schedule")
+    if rc != 0:
+        raise ValueError(f"or_sweep failed ({rc})")
+    if counts is not None:
+        counts.att += a.value
+        counts.det += d.value
+    return h.value
+
+
+def run(lat: np.ndarray, p: float, q: float, seed: int, t0: int, n: int, H0: int,
+        check: bool = False, counts: Counts | None = None) -> int:
+    """Sweeps ``t0 .. t0+n-1`` of the tiled dynamics; returns the new H0."""
+    for s in range(t0, t0 + n):
+        H0 = sweep(lat, p, q, seed, s, H0, check=check, counts=counts)
+    return H0
+
+
+def block_sweep(blk: np.ndarray, C: int, seed: int, s: int, block_id: int, p: float,
+                q: float, site00=(-1, -1), check: bool = False) -> tuple:
+    """One sweep of a single device-level block given as its (By, Bx) cut-out.
+
+    Returns (dh00, n_att, n_det).  Blocks are independent within a sweep, so
+    this reproduces the tiled sweep of any block of any lattice size.
+    """
+    _check_lattice(blk)
+    By, Bx = blk.shape
+    dh, a, d = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    touched = np.zeros(2 * Bx * By, dtype=np.uint8) if check else None
+    rc = lib().or_block_sweep(_ptr(blk, _u8p), Bx, By, C, seed, s, block_id,
+                              threshold(p), threshold(q), site00[0], site00[1],
+                              ctypes.byref(dh), ctypes.byref(a), ctypes.byref(d),
+                              _ptr(touched, _u8p) if check else None)
+    if rc != 0:
+        raise AssertionError("bond conflict inside one step of the tiled schedule")
+    return dh.value, a.value, d.value
+
+
+def rsu_sweep(lat: np.ndarray, p: float, q: float, seed: int, t: int, H0: int,
+              counts: Counts | None = None) -> int:
+    """One MCS (N attempts) of the random-sequential judge; returns new H0."""
+    _check_lattice(lat)
+    Ly, Lx = lat.shape
+    h = ctypes.c_int64(H0)
+    a, d = ctypes.c_int64(0), ctypes.c_int64(0)
+    lib().or_rsu_sweep(_ptr(lat, _u8p), Lx, Ly, threshold(p), threshold(q), seed, t,
+                       ctypes.byref(h), ctypes.byref(a), ctypes.byref(d))
+    if counts is not None:
+        counts.att += a.value
+        counts.det += d.value
+    return h.value
+
+
+def rsu_run(lat, p, q, seed, t0, n, H0, counts=None) -> int:
+    for t in range(t0, t0 + n):
+        H0 = rsu_sweep(lat, p, q, seed, t, H0, counts=counts)
+    return H0
+
+
+# --------------------------------------------------------------------------
+# Heights and width
+# --------------------------------------------------------------------------
+def heights(lat: np.ndarray, H0: int) -> np.ndarray:
+    _check_lattice(lat)
+    Ly, Lx = lat.shape
+    h = np.empty((Ly, Lx), dtype=np.int64)
+    lib().or_heights(_ptr(lat, _u8p), Lx, Ly, H0, _ptr(h, _i64p))
+    return h
+
+
+def width_sums(lat: np.ndarray, H0: int) -> tuple:
+    """(S1, S2) = (sum h, sum h^2), exact; raises OverflowError past int64."""
+    _check_lattice(lat)
+    Ly, Lx = lat.shape
+    s1, s2 = ctypes.c_int64(), ctypes.c_int64()
+    if lib().or_width(_ptr(lat, _u8p), Lx, Ly, H0, ctypes.byref(s1), ctypes.byref(s2)) != 0:
+        raise OverflowError("width sums exceed int64")
+    return s1.value, s2.value
+
+
+def w2(S1: int, S2: int, N: int) -> float:
+    """W^2 = S2/N - (S1/N)^2 from exact sums (numerator in Python integers)."""
+    return (N * S2 - S1 * S1) / (N * N)
+
+
+def ensemble(Lx: int, Ly: int, p: float, q: float, seed0: int, R: int, tmax: int,
+             rsu: bool = False) -> np.ndarray:
+    """(S1, S2) after every MCS t = 1..tmax of R flat-start realizations with
+    seeds seed0 .. seed0+R-1; returns an int64 array of shape (R, tmax, 2)."""
+    out = np.zeros((R, tmax, 2), dtype=np.int64)
+    rc = lib().or_ensemble(Lx, Ly, float(p), float(q), seed0, R, tmax, int(rsu),
+                           _ptr(out, _i64p))
+    if rc != 0:
+        raise RuntimeError(f"or_ensemble failed ({rc})")
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(int(n))
