@@ -1,0 +1,121 @@
+/*
+ * okpz -- octahedron-model KPZ growth on AMD MI355X (gfx950).
+ *
+ * C ABI of the hot path of Kelling & Odor, "Extremely large scale simulation
+ * of a KPZ model using graphics cards" (arXiv:1110.6745): Monte Carlo sweeps
+ * of the generalized Kawasaki rule (Eq. (1)) on a two-bit-per-site slope
+ * lattice (Sec. II) and the exact surface width (Sec. I height
+ * reconstruction, Eq. (Wdef)).
+ *
+ * Conventions shared by every call:
+ *  - Return value 0 (OKPZ_OK) on success, a negative OKPZ_E* code otherwise;
+ *    okpz_last_error() then gives a message (thread-local).
+ *  - A handle is not thread-safe; distinct handles may be used from distinct
+ *    threads.  Device work is issued on the handle's HIP stream; calls that
+ *    return host results synchronize that stream.
+ *  - Lattice sizes: Lx, Ly multiples of 32, 32 <= Lx, Ly <= 2^20.
+ *  - Canonical host lattice layout (get/set calls): one byte per site,
+ *    row-major, byte[y*Lx + x]; bit 0 = [sigma_x(x,y) = +1], bit 1 =
+ *    [sigma_y(x,y) = +1], where sigma_x(x,y) = h(x+1,y) - h(x,y) and
+ *    sigma_y(x,y) = h(x,y+1) - h(x,y) on the periodic lattice.
+ *  - Heights: h(x,y) = H0 + sum_{k<y} sigma_y(0,k) + sum_{l<x} sigma_x(l,y),
+ *    H0 = h(0,0), tracked exactly by the library.
+ */
+#ifndef OKPZ_H
+#define OKPZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OKPZ_OK 0
+#define OKPZ_EINVAL (-22)    /* bad argument: size, probability, time, buffer */
+#define OKPZ_ENOMEM (-12)    /* device or host allocation failed, buffer too small */
+#define OKPZ_EOVERFLOW (-75) /* an exact sum does not fit a signed 64-bit integer */
+#define OKPZ_EDEVICE (-5)    /* a HIP runtime error; message kept */
+#define OKPZ_EBUSY (-16)     /* resource limit (slots, bytes) reached */
+
+typedef struct okpz_sim okpz_sim; /* opaque; one simulated lattice */
+
+/* Geometry of the two-level dead-border decomposition (Sec. II): block sides
+ * Bx, By = largest power of two dividing Lx, Ly, at most 256; thread-cell side
+ * C = min(8, Bx, By).  Depends on the lattice size only. */
+int okpz_geometry(int64_t Lx, int64_t Ly, int32_t *Bx, int32_t *By, int32_t *C);
+
+/* Device bytes a simulation of this size needs (two lattice copies plus
+ * width scratch); what okpz_init_on's buffer must provide. */
+size_t okpz_required_bytes(int64_t Lx, int64_t Ly);
+
+/* Create a simulation of an Lx x Ly periodic lattice in the flat zig-zag
+ * state h = (x+y) mod 2 (Sec. III: W^2(L,0) = 1/4), time t = 0, attachment
+ * probability p and detachment probability q in [0,1] (Eq. (1)), and the
+ * seed that keys every random decision.  The library allocates device memory
+ * and a stream.  *out receives the handle (NULL on error). */
+int okpz_init(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed);
+
+/* As okpz_init, but on caller-owned device memory (dev_buf, at least
+ * okpz_required_bytes bytes, 256-byte aligned) and a caller-owned HIP stream
+ * (hipStream_t passed as void*, NULL = default stream).  The caller keeps
+ * both alive until okpz_free. */
+int okpz_init_on(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
+                 void *dev_buf, size_t bytes, void *hip_stream);
+
+/* Advance by n_mcs >= 0 Monte Carlo steps (Sec. II: one MCS = one overall
+ * update, block-decomposition origin moved at every MCS).  Asynchronous on the
+ * handle's stream.  Sweep indices must stay below 2^32. */
+int okpz_sweep(okpz_sim *s, int64_t n_mcs);
+
+/* Advance to MCS t (t >= current time; t == current time just measures) and
+ * return the exact sums sum_h = sum h(x,y) and sum_h2 = sum h(x,y)^2 over all
+ * sites (Eq. (Wdef): W^2 = sum_h2/N - (sum_h/N)^2, N = Lx*Ly).  Synchronous.
+ * OKPZ_EOVERFLOW if a sum leaves the signed 64-bit range. */
+int okpz_width(okpz_sim *s, int64_t t, int64_t *sum_h, int64_t *sum_h2);
+
+/* Same measurement as okpz_width at the current time, returning W^2 in double
+ * from the exact integer numerator N*S2 - S1^2 (independent of H0). */
+int okpz_w2(okpz_sim *s, double *w2);
+
+/* Current time in MCS, and the absolute height H0 = h(0,0) (synchronous). */
+int okpz_time(const okpz_sim *s, int64_t *t);
+int okpz_h0(okpz_sim *s, int64_t *h0);
+
+/* The handle's HIP stream (as void*). */
+void *okpz_stream(const okpz_sim *s);
+
+/* Copy the whole lattice to host memory in the canonical layout
+ * (bytes >= Lx*Ly).  Synchronous. */
+int okpz_get_lattice(okpz_sim *s, uint8_t *host, size_t bytes);
+
+/* Copy rows y0 .. y0+nrows-1 (mod Ly) in the canonical layout
+ * (bytes >= nrows*Lx).  Synchronous.  For sampled checks of large lattices. */
+int okpz_get_rows(okpz_sim *s, int64_t y0, int64_t nrows, uint8_t *host, size_t bytes);
+
+/* Replace the state: canonical lattice (bytes >= Lx*Ly), absolute height H0
+ * of site (0,0) and current time t >= 0.  The lattice must be a valid slope
+ * field (zero row sums of sigma_x, zero column sums of sigma_y, closed
+ * plaquettes), else OKPZ_EINVAL.  Synchronous. */
+int okpz_set_lattice(okpz_sim *s, const uint8_t *host, size_t bytes, int64_t H0, int64_t t);
+
+/* Checkpoint: okpz_save writes the full state (parameters, time, H0, packed
+ * lattice) to buf; with buf == NULL it only stores the needed size in *bytes.
+ * okpz_load creates a new handle from such a buffer; continuing it gives the
+ * same trajectory bit for bit as the original. */
+int okpz_save(okpz_sim *s, void *buf, size_t *bytes);
+int okpz_load(okpz_sim **out, const void *buf, size_t bytes);
+
+/* Wait for the handle's stream. */
+int okpz_sync(okpz_sim *s);
+
+/* Release the handle and everything the library allocated for it. */
+int okpz_free(okpz_sim *s);
+
+/* Message of the last error on this thread ("" if none). */
+const char *okpz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OKPZ_H */

@@ -1,0 +1,577 @@
+// C ABI of the okpz library: handles, validation, stream order, exact int64
+// width combination, lattice up/download and checkpoints.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "okpz.h"
+#include "okpz_internal.h"
+
+struct okpz_sim {
+    int64_t Lx, Ly;
+    int32_t W;
+    okpz::Geometry g;
+    double p, q;
+    uint64_t seed;
+    uint32_t k0, k1;
+    uint64_t Tp, Tq;
+    uint32_t *buf[2];
+    int cur;
+    int32_t ox;
+    int64_t t;
+    int64_t *d_h0;
+    int64_t *d_out;
+    int64_t *d_rows;
+    hipStream_t stream;
+    bool own_stream;
+    void *mem;
+    bool own_mem;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(OKPZ_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                    \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+size_t plane_bytes(int64_t Lx, int64_t Ly) { return 2 * (size_t)Ly * (size_t)(Lx / 32) * 4; }
+
+bool size_ok(int64_t L) { return L >= 32 && L <= (int64_t(1) << 20) && L % 32 == 0; }
+
+bool prob_ok(double v) { return v >= 0.0 && v <= 1.0; }
+
+__global__ void init_flat_kernel(uint32_t *planes, int32_t Ly, int32_t W, int64_t *h0)
+{
+    // h(x,y) = (x+y) mod 2: sigma_x = sigma_y = +1 exactly where x+y is even
+    const size_t n = 2 * (size_t)Ly * W;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t y = (e / W) % Ly;
+        planes[e] = (y & 1) ? 0xAAAAAAAAu : 0x55555555u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *h0 = 0;
+}
+
+__global__ void set_h0_kernel(int64_t *h0, int64_t v) { *h0 = v; }
+
+int alloc_state(okpz_sim *s, void *dev_buf, size_t bytes, void *stream)
+{
+    const size_t pb = align_up(plane_bytes(s->Lx, s->Ly));
+    const size_t need = okpz_required_bytes(s->Lx, s->Ly);
+    if (dev_buf) {
+        if (bytes < need)
+            return fail(OKPZ_ENOMEM, "buffer of %zu bytes, %zu needed", bytes, need);
+        if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign)
+            return fail(OKPZ_EINVAL, "device buffer must be %zu-byte aligned", kAlign);
+        s->mem = dev_buf;
+        s->own_mem = false;
+        s->stream = reinterpret_cast<hipStream_t>(stream);
+        s->own_stream = false;
+    } else {
+        void *m = nullptr;
+        hipError_t e = hipMalloc(&m, need);
+        if (e != hipSuccess) return fail(OKPZ_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+        s->mem = m;
+        s->own_mem = true;
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            (void)hipFree(m);
+            s->mem = nullptr;
+            return hip_fail(e, "hipStreamCreate");
+        }
+        s->own_stream = true;
+    }
+    char *base = static_cast<char *>(s->mem);
+    s->buf[0] = reinterpret_cast<uint32_t *>(base);
+    s->buf[1] = reinterpret_cast<uint32_t *>(base + pb);
+    s->d_h0 = reinterpret_cast<int64_t *>(base + 2 * pb);
+    s->d_out = reinterpret_cast<int64_t *>(base + 2 * pb + kAlign);
+    s->d_rows = reinterpret_cast<int64_t *>(base + 2 * pb + 2 * kAlign);
+    return OKPZ_OK;
+}
+
+void release(okpz_sim *s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->own_mem && s->mem) (void)hipFree(s->mem);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int make_sim(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
+             void *dev_buf, size_t bytes, void *stream)
+{
+    if (!out) return fail(OKPZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!size_ok(Lx) || !size_ok(Ly))
+        return fail(OKPZ_EINVAL, "lattice %lldx%lld: sides must be multiples of 32 in [32, 2^20]",
+                    (long long)Lx, (long long)Ly);
+    if (!prob_ok(p) || !prob_ok(q)) return fail(OKPZ_EINVAL, "p=%g q=%g must lie in [0,1]", p, q);
+    okpz_sim *s = new (std::nothrow) okpz_sim();
+    if (!s) return fail(OKPZ_ENOMEM, "host allocation failed");
+    s->Lx = Lx;
+    s->Ly = Ly;
+    s->W = (int32_t)(Lx / 32);
+    okpz::geometry_of(Lx, Ly, &s->g);
+    s->p = p;
+    s->q = q;
+    s->seed = seed;
+    s->k0 = (uint32_t)(seed & 0xffffffffu);
+    s->k1 = (uint32_t)(seed >> 32);
+    s->Tp = okpz::threshold_of(p);
+    s->Tq = okpz::threshold_of(q);
+    s->cur = 0;
+    s->ox = 0;
+    s->t = 0;
+    int rc = alloc_state(s, dev_buf, bytes, stream);
+    if (rc != OKPZ_OK) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return OKPZ_OK;
+}
+
+int launch_flat(okpz_sim *s)
+{
+    const size_t n = 2 * (size_t)s->Ly * s->W;
+    const int threads = 256;
+    const int blocks = (int)std::min<size_t>((n + threads - 1) / threads, 65536);
+    hipLaunchKernelGGL(init_flat_kernel, dim3(blocks), dim3(threads), 0, s->stream, s->buf[0],
+                       (int32_t)s->Ly, s->W, s->d_h0);
+    HIP_TRY(hipGetLastError());
+    s->cur = 0;
+    s->ox = 0;
+    s->t = 0;
+    return OKPZ_OK;
+}
+
+// physical column x of stored copy with offset ox: stored column (x - ox) mod Lx
+inline int64_t stored_col(int64_t x, int32_t ox, int64_t Lx) { return ((x - ox) % Lx + Lx) % Lx; }
+
+int download_rows(okpz_sim *s, int64_t y0, int64_t n, std::vector<uint32_t> &pl0,
+                  std::vector<uint32_t> &pl1)
+{
+    const size_t W = (size_t)s->W;
+    pl0.resize(n * W);
+    pl1.resize(n * W);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    int64_t done = 0;
+    while (done < n) {
+        const int64_t y = (y0 + done) % s->Ly;
+        const int64_t run = std::min<int64_t>(n - done, s->Ly - y);
+        const uint32_t *src0 = s->buf[s->cur] + (size_t)y * W;
+        const uint32_t *src1 = s->buf[s->cur] + ((size_t)s->Ly + y) * W;
+        HIP_TRY(hipMemcpy(pl0.data() + done * W, src0, run * W * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(pl1.data() + done * W, src1, run * W * 4, hipMemcpyDeviceToHost));
+        done += run;
+    }
+    return OKPZ_OK;
+}
+
+void unpack_rows(const okpz_sim *s, int64_t n, const std::vector<uint32_t> &pl0,
+                 const std::vector<uint32_t> &pl1, uint8_t *host)
+{
+    const int64_t Lx = s->Lx;
+    const size_t W = (size_t)s->W;
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t x = 0; x < Lx; ++x) {
+            const int64_t c = stored_col(x, s->ox, Lx);
+            const uint32_t bx = (pl0[r * W + (c >> 5)] >> (c & 31)) & 1u;
+            const uint32_t by = (pl1[r * W + (c >> 5)] >> (c & 31)) & 1u;
+            host[r * Lx + x] = (uint8_t)(bx | (by << 1));
+        }
+}
+
+bool valid_slope_field(const uint8_t *h, int64_t Lx, int64_t Ly, std::string &why)
+{
+    for (int64_t i = 0; i < Lx * Ly; ++i)
+        if (h[i] > 3) {
+            why = "byte > 3";
+            return false;
+        }
+    for (int64_t y = 0; y < Ly; ++y) {
+        int64_t sum = 0;
+        for (int64_t x = 0; x < Lx; ++x) sum += (h[y * Lx + x] & 1) ? 1 : -1;
+        if (sum) {
+            why = "sigma_x row sum not zero";
+            return false;
+        }
+    }
+    for (int64_t x = 0; x < Lx; ++x) {
+        int64_t sum = 0;
+        for (int64_t y = 0; y < Ly; ++y) sum += (h[y * Lx + x] & 2) ? 1 : -1;
+        if (sum) {
+            why = "sigma_y column sum not zero";
+            return false;
+        }
+    }
+    for (int64_t y = 0; y < Ly; ++y)
+        for (int64_t x = 0; x < Lx; ++x) {
+            const int64_t x1 = (x + 1) % Lx, y1 = (y + 1) % Ly;
+            const int a = (h[y * Lx + x] & 1) ? 1 : -1;
+            const int b = (h[y * Lx + x1] & 2) ? 1 : -1;
+            const int c = (h[y1 * Lx + x] & 1) ? 1 : -1;
+            const int d = (h[y * Lx + x] & 2) ? 1 : -1;
+            if (a + b - c - d != 0) {
+                why = "plaquette not closed";
+                return false;
+            }
+        }
+    return true;
+}
+
+int upload_lattice(okpz_sim *s, const uint8_t *host)
+{
+    const size_t W = (size_t)s->W;
+    std::vector<uint32_t> planes(2 * (size_t)s->Ly * W, 0u);
+    for (int64_t y = 0; y < s->Ly; ++y)
+        for (int64_t x = 0; x < s->Lx; ++x) {
+            const uint8_t b = host[y * s->Lx + x];
+            if (b & 1) planes[(size_t)y * W + (x >> 5)] |= 1u << (x & 31);
+            if (b & 2) planes[((size_t)s->Ly + y) * W + (x >> 5)] |= 1u << (x & 31);
+        }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(s->buf[0], planes.data(), planes.size() * 4, hipMemcpyHostToDevice));
+    s->cur = 0;
+    s->ox = 0;
+    return OKPZ_OK;
+}
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t pad;
+    int64_t Lx, Ly;
+    double p, q;
+    uint64_t seed;
+    int64_t t, H0;
+    int32_t ox, pad2;
+};
+
+}  // namespace
+
+namespace okpz {
+
+bool geometry_of(int64_t Lx, int64_t Ly, Geometry *g)
+{
+    auto side = [](int64_t L) {
+        int64_t b = 1;
+        while (b < 256 && L % (b * 2) == 0) b *= 2;
+        return (int32_t)b;
+    };
+    g->Bx = side(Lx);
+    g->By = side(Ly);
+    g->C = std::min<int32_t>(8, std::min(g->Bx, g->By));
+    return true;
+}
+
+uint64_t threshold_of(double prob)
+{
+    if (!(prob > 0.0)) return 0;
+    if (prob >= 1.0) return uint64_t(1) << 32;
+    const long long r = std::llround(std::ldexp(prob, 32));
+    return (uint64_t)std::clamp<long long>(r, 0, 1LL << 32);
+}
+
+}  // namespace okpz
+
+extern "C" {
+
+int okpz_geometry(int64_t Lx, int64_t Ly, int32_t *Bx, int32_t *By, int32_t *C)
+{
+    if (!size_ok(Lx) || !size_ok(Ly))
+        return fail(OKPZ_EINVAL, "lattice sides must be multiples of 32 in [32, 2^20]");
+    okpz::Geometry g;
+    okpz::geometry_of(Lx, Ly, &g);
+    if (Bx) *Bx = g.Bx;
+    if (By) *By = g.By;
+    if (C) *C = g.C;
+    return OKPZ_OK;
+}
+
+size_t okpz_required_bytes(int64_t Lx, int64_t Ly)
+{
+    if (!size_ok(Lx) || !size_ok(Ly)) return 0;
+    return 2 * align_up(plane_bytes(Lx, Ly)) + 2 * kAlign +
+           align_up(okpz::width_scratch_words(Ly) * sizeof(int64_t));
+}
+
+int okpz_init(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed)
+{
+    return okpz_init_on(out, Lx, Ly, p, q, seed, nullptr, 0, nullptr);
+}
+
+int okpz_init_on(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
+                 void *dev_buf, size_t bytes, void *hip_stream)
+{
+    okpz_sim *s = nullptr;
+    int rc = make_sim(&s, Lx, Ly, p, q, seed, dev_buf, bytes, hip_stream);
+    if (rc != OKPZ_OK) return rc;
+    rc = launch_flat(s);
+    if (rc != OKPZ_OK) {
+        release(s);
+        return rc;
+    }
+    *out = s;
+    return OKPZ_OK;
+}
+
+int okpz_sweep(okpz_sim *s, int64_t n_mcs)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    if (n_mcs < 0) return fail(OKPZ_EINVAL, "n_mcs < 0");
+    if (s->t + n_mcs > (int64_t(1) << 32))
+        return fail(OKPZ_EINVAL, "sweep index would pass 2^32");
+    okpz::SweepLaunch a{};
+    a.h0 = s->d_h0;
+    a.Lx = (int32_t)s->Lx;
+    a.Ly = (int32_t)s->Ly;
+    a.W = s->W;
+    a.Bx = s->g.Bx;
+    a.By = s->g.By;
+    a.nbx = (int32_t)(s->Lx / s->g.Bx);
+    a.nby = (int32_t)(s->Ly / s->g.By);
+    a.k0 = s->k0;
+    a.k1 = s->k1;
+    a.Tp = s->Tp;
+    a.Tq = s->Tq;
+    const bool trivial = (s->Tp == 0 || s->Tp == (uint64_t(1) << 32)) &&
+                         (s->Tq == 0 || s->Tq == (uint64_t(1) << 32));
+    a.need_accept_draws = trivial ? 0 : 1;
+    for (int64_t n = 0; n < n_mcs; ++n) {
+        const uint32_t sw = (uint32_t)s->t;
+        int32_t sx, sy;
+        okpz::block_shift(s->k0, s->k1, sw, s->g, &sx, &sy);
+        const int64_t x00 = (s->Lx - sx) % s->Lx, y00 = (s->Ly - sy) % s->Ly;
+        a.blk00 = (int32_t)((y00 / s->g.By) * a.nbx + x00 / s->g.Bx);
+        a.u00 = (int32_t)(x00 % s->g.Bx);
+        a.v00 = (int32_t)(y00 % s->g.By);
+        a.src = s->buf[s->cur];
+        a.dst = s->buf[s->cur ^ 1];
+        a.ox_src = s->ox;
+        a.sx = sx;
+        a.sy = sy;
+        a.s = sw;
+        HIP_TRY(okpz::launch_sweep(a, s->stream));
+        s->cur ^= 1;
+        s->ox = sx;
+        s->t += 1;
+    }
+    return OKPZ_OK;
+}
+
+static int measure(okpz_sim *s, __int128 *S1r, __int128 *S2r, int64_t *H0)
+{
+    okpz::LatticeView v{s->buf[s->cur], (int32_t)s->Lx, (int32_t)s->Ly, s->W, s->ox};
+    HIP_TRY(okpz::launch_width(v, s->d_rows, s->d_out, s->stream));
+    int64_t host[5];
+    HIP_TRY(hipMemcpyAsync(host, s->d_out, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(host + 4, s->d_h0, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    *S1r = (__int128)(((unsigned __int128)(uint64_t)host[1] << 64) | (uint64_t)host[0]);
+    *S2r = (__int128)(((unsigned __int128)(uint64_t)host[3] << 64) | (uint64_t)host[2]);
+    *H0 = host[4];
+    return OKPZ_OK;
+}
+
+int okpz_width(okpz_sim *s, int64_t t, int64_t *sum_h, int64_t *sum_h2)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    if (t < s->t) return fail(OKPZ_EINVAL, "t=%lld is before the current time %lld", (long long)t,
+                              (long long)s->t);
+    int rc = okpz_sweep(s, t - s->t);
+    if (rc != OKPZ_OK) return rc;
+    __int128 S1r, S2r;
+    int64_t H0;
+    rc = measure(s, &S1r, &S2r, &H0);
+    if (rc != OKPZ_OK) return rc;
+    // S1 = S1' + N H0, S2 = S2' + 2 H0 S1' + N H0^2, exact in 128 bits
+    const __int128 N = (__int128)s->Lx * s->Ly;
+    const __int128 S1 = S1r + N * H0;
+    const __int128 S2 = S2r + 2 * (__int128)H0 * S1r + N * (__int128)H0 * H0;
+    const __int128 lim = (__int128)1 << 63;
+    if (S1 >= lim || S1 < -lim || S2 >= lim || S2 < 0)
+        return fail(OKPZ_EOVERFLOW, "width sums exceed int64 at t=%lld", (long long)s->t);
+    if (sum_h) *sum_h = (int64_t)S1;
+    if (sum_h2) *sum_h2 = (int64_t)S2;
+    return OKPZ_OK;
+}
+
+int okpz_w2(okpz_sim *s, double *w2)
+{
+    if (!s || !w2) return fail(OKPZ_EINVAL, "null argument");
+    __int128 S1r, S2r;
+    int64_t H0;
+    int rc = measure(s, &S1r, &S2r, &H0);
+    if (rc != OKPZ_OK) return rc;
+    const __int128 N = (__int128)s->Lx * s->Ly;
+    const __int128 num = N * S2r - S1r * S1r;  // independent of H0
+    *w2 = (double)num / ((double)N * (double)N);
+    return OKPZ_OK;
+}
+
+int okpz_time(const okpz_sim *s, int64_t *t)
+{
+    if (!s || !t) return fail(OKPZ_EINVAL, "null argument");
+    *t = s->t;
+    return OKPZ_OK;
+}
+
+int okpz_h0(okpz_sim *s, int64_t *h0)
+{
+    if (!s || !h0) return fail(OKPZ_EINVAL, "null argument");
+    HIP_TRY(hipMemcpyAsync(h0, s->d_h0, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return OKPZ_OK;
+}
+
+void *okpz_stream(const okpz_sim *s) { return s ? reinterpret_cast<void *>(s->stream) : nullptr; }
+
+int okpz_get_rows(okpz_sim *s, int64_t y0, int64_t nrows, uint8_t *host, size_t bytes)
+{
+    if (!s || !host) return fail(OKPZ_EINVAL, "null argument");
+    if (nrows < 0 || nrows > s->Ly) return fail(OKPZ_EINVAL, "nrows out of range");
+    if (bytes < (size_t)(nrows * s->Lx)) return fail(OKPZ_EINVAL, "host buffer too small");
+    y0 = ((y0 % s->Ly) + s->Ly) % s->Ly;
+    std::vector<uint32_t> p0, p1;
+    int rc = download_rows(s, y0, nrows, p0, p1);
+    if (rc != OKPZ_OK) return rc;
+    unpack_rows(s, nrows, p0, p1, host);
+    return OKPZ_OK;
+}
+
+int okpz_get_lattice(okpz_sim *s, uint8_t *host, size_t bytes)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    return okpz_get_rows(s, 0, s->Ly, host, bytes);
+}
+
+int okpz_set_lattice(okpz_sim *s, const uint8_t *host, size_t bytes, int64_t H0, int64_t t)
+{
+    if (!s || !host) return fail(OKPZ_EINVAL, "null argument");
+    if (bytes < (size_t)(s->Lx * s->Ly)) return fail(OKPZ_EINVAL, "host buffer too small");
+    if (t < 0 || t >= (int64_t(1) << 32)) return fail(OKPZ_EINVAL, "t out of range");
+    std::string why;
+    if (!valid_slope_field(host, s->Lx, s->Ly, why))
+        return fail(OKPZ_EINVAL, "not a valid slope field: %s", why.c_str());
+    int rc = upload_lattice(s, host);
+    if (rc != OKPZ_OK) return rc;
+    hipLaunchKernelGGL(set_h0_kernel, dim3(1), dim3(1), 0, s->stream, s->d_h0, H0);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->t = t;
+    return OKPZ_OK;
+}
+
+int okpz_save(okpz_sim *s, void *buf, size_t *bytes)
+{
+    if (!s || !bytes) return fail(OKPZ_EINVAL, "null argument");
+    const size_t pb = plane_bytes(s->Lx, s->Ly);
+    const size_t need = sizeof(CkptHeader) + pb;
+    if (!buf) {
+        *bytes = need;
+        return OKPZ_OK;
+    }
+    if (*bytes < need) return fail(OKPZ_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
+    int64_t H0;
+    int rc = okpz_h0(s, &H0);
+    if (rc != OKPZ_OK) return rc;
+    CkptHeader h{};
+    std::memcpy(h.magic, "OKPZCKP1", 8);
+    h.version = 1;
+    h.Lx = s->Lx;
+    h.Ly = s->Ly;
+    h.p = s->p;
+    h.q = s->q;
+    h.seed = s->seed;
+    h.t = s->t;
+    h.H0 = H0;
+    h.ox = s->ox;
+    std::memcpy(buf, &h, sizeof h);
+    HIP_TRY(hipMemcpy(static_cast<char *>(buf) + sizeof h, s->buf[s->cur], pb, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return OKPZ_OK;
+}
+
+int okpz_load(okpz_sim **out, const void *buf, size_t bytes)
+{
+    if (!out || !buf) return fail(OKPZ_EINVAL, "null argument");
+    *out = nullptr;
+    CkptHeader h;
+    if (bytes < sizeof h) return fail(OKPZ_EINVAL, "checkpoint truncated");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, "OKPZCKP1", 8) != 0 || h.version != 1)
+        return fail(OKPZ_EINVAL, "not an okpz checkpoint");
+    if (!size_ok(h.Lx) || !size_ok(h.Ly) || h.ox < 0 || h.ox >= h.Lx || h.t < 0)
+        return fail(OKPZ_EINVAL, "corrupt checkpoint header");
+    const size_t pb = plane_bytes(h.Lx, h.Ly);
+    if (bytes < sizeof h + pb) return fail(OKPZ_EINVAL, "checkpoint truncated");
+    okpz_sim *s = nullptr;
+    int rc = make_sim(&s, h.Lx, h.Ly, h.p, h.q, h.seed, nullptr, 0, nullptr);
+    if (rc != OKPZ_OK) return rc;
+    hipError_t e = hipMemcpy(s->buf[0], static_cast<const char *>(buf) + sizeof h, pb,
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release(s);
+        return hip_fail(e, "hipMemcpy(checkpoint)");
+    }
+    hipLaunchKernelGGL(set_h0_kernel, dim3(1), dim3(1), 0, s->stream, s->d_h0, h.H0);
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        release(s);
+        return hip_fail(e, "restore");
+    }
+    s->cur = 0;
+    s->ox = h.ox;
+    s->t = h.t;
+    *out = s;
+    return OKPZ_OK;
+}
+
+int okpz_sync(okpz_sim *s)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return OKPZ_OK;
+}
+
+int okpz_free(okpz_sim *s)
+{
+    if (!s) return OKPZ_OK;
+    release(s);
+    return OKPZ_OK;
+}
+
+const char *okpz_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal declarations of the okpz HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace okpz {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based bijection
+// keyed by the simulation seed, so every random decision of the dynamics is a
+// pure function of (seed, counter) and independent of execution order.
+struct Ctr4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = Ctr4{(uint32_t)(m1 >> 32) ^ c.y ^ k0, (uint32_t)m1, (uint32_t)(m0 >> 32) ^ c.w ^ k1,
+                 (uint32_t)m0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Stream tags (fourth counter word) of the random decisions.
+enum : uint32_t { kTagSite = 0, kTagOrigin = 1, kTagShift = 2, kTagAccept = 4 };
+
+// floor(r * n / 2^32): uniform integer below n from a 32-bit draw.
+__host__ __device__ __forceinline__ uint32_t below(uint32_t r, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)r * n) >> 32);
+}
+
+// Decomposition geometry of a lattice (Sec. II): block sides and thread cell.
+struct Geometry {
+    int32_t Bx, By, C;
+};
+
+bool geometry_of(int64_t Lx, int64_t Ly, Geometry *g);
+uint64_t threshold_of(double prob);
+
+// Device layout of one lattice copy: two bit planes (0 = sigma_x bits,
+// 1 = sigma_y bits), each Ly rows of W = Lx/32 words; bit (x' & 31) of word
+// (x' >> 5) of row y holds stored column x', where stored column x' is the
+// physical column (x' + ox) mod Lx for the copy's offset ox.
+struct LatticeView {
+    uint32_t *planes;  // 2 * Ly * W words
+    int32_t Lx, Ly, W;
+    int32_t ox;        // stored-column offset
+};
+
+struct SweepLaunch {
+    const uint32_t *src;
+    uint32_t *dst;
+    int64_t *h0;
+    int32_t Lx, Ly, W;
+    int32_t Bx, By, nbx, nby;
+    int32_t ox_src;
+    int32_t sx, sy;
+    uint32_t s;
+    uint32_t k0, k1;
+    uint64_t Tp, Tq;
+    int32_t blk00, u00, v00;
+    int32_t need_accept_draws;
+};
+
+// Block shift of sweep s (host side; the kernel uses the same values).
+void block_shift(uint32_t k0, uint32_t k1, uint32_t s, const Geometry &g, int32_t *sx,
+                 int32_t *sy);
+
+hipError_t launch_init(uint32_t *planes, int32_t Ly, int32_t W, hipStream_t st);
+hipError_t launch_sweep(const SweepLaunch &a, hipStream_t st);
+
+// Width: per-row partial sums into `rows` scratch (3 * Ly int64), then one
+// workgroup combines them into out[0..3] = {S1' lo, S1' hi, S2' lo, S2' hi}
+// (128-bit two's complement halves of the sums relative to H0).
+hipError_t launch_width(const LatticeView &v, int64_t *rows, int64_t *out, hipStream_t st);
+
+size_t width_scratch_words(int64_t Ly);
+
+}  // namespace okpz

@@ -1,0 +1,209 @@
+"""Python binding of the okpz C ABI (``include/okpz.h``).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library ``libokpz.so`` built in this directory.  Importing this module fails
+loudly if the library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+# torch is the memory/stream layer of this package.  Importing it first makes
+# the process load one HIP runtime (torch's); the library then binds to it by
+# its soname instead of loading a second runtime.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libokpz.so")
+
+OKPZ_OK = 0
+OKPZ_EINVAL = -22
+OKPZ_ENOMEM = -12
+OKPZ_EOVERFLOW = -75
+OKPZ_EDEVICE = -5
+OKPZ_EBUSY = -16
+
+
+class OkpzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"okpz error {code}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"okpz HIP library not built: {LIB_PATH} is missing "
+                      "(run __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_sz = ctypes.c_size_t
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("okpz_geometry", ctypes.c_int, _i64, _i64, _i32p, _i32p, _i32p)
+_sig("okpz_required_bytes", _sz, _i64, _i64)
+_sig("okpz_init", ctypes.c_int, ctypes.POINTER(_vp), _i64, _i64, ctypes.c_double,
+     ctypes.c_double, ctypes.c_uint64)
+_sig("okpz_init_on", ctypes.c_int, ctypes.POINTER(_vp), _i64, _i64, ctypes.c_double,
+     ctypes.c_double, ctypes.c_uint64, _vp, _sz, _vp)
+_sig("okpz_sweep", ctypes.c_int, _vp, _i64)
+_sig("okpz_width", ctypes.c_int, _vp, _i64, _i64p, _i64p)
+_sig("okpz_w2", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double))
+_sig("okpz_time", ctypes.c_int, _vp, _i64p)
+_sig("okpz_h0", ctypes.c_int, _vp, _i64p)
+_sig("okpz_stream", _vp, _vp)
+_sig("okpz_get_lattice", ctypes.c_int, _vp, _u8p, _sz)
+_sig("okpz_get_rows", ctypes.c_int, _vp, _i64, _i64, _u8p, _sz)
+_sig("okpz_set_lattice", ctypes.c_int, _vp, _u8p, _sz, _i64, _i64)
+_sig("okpz_save", ctypes.c_int, _vp, _vp, ctypes.POINTER(_sz))
+_sig("okpz_load", ctypes.c_int, ctypes.POINTER(_vp), _vp, _sz)
+_sig("okpz_sync", ctypes.c_int, _vp)
+_sig("okpz_free", ctypes.c_int, _vp)
+_sig("okpz_last_error", ctypes.c_char_p)
+
+EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on", "okpz_sweep",
+            "okpz_width", "okpz_w2", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
+            "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_sync",
+            "okpz_free", "okpz_last_error"]
+
+
+def _check(rc: int) -> None:
+    if rc != OKPZ_OK:
+        raise OkpzError(rc, _lib.okpz_last_error().decode(errors="replace"))
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+# ---- functions with the C names -------------------------------------------
+def okpz_geometry(Lx: int, Ly: int) -> tuple:
+    bx, by, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.okpz_geometry(Lx, Ly, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(c)))
+    return bx.value, by.value, c.value
+
+
+def okpz_required_bytes(Lx: int, Ly: int) -> int:
+    return int(_lib.okpz_required_bytes(Lx, Ly))
+
+
+def okpz_init(Lx: int, Ly: int, p: float, q: float, seed: int) -> "Sim":
+    h = _vp()
+    _check(_lib.okpz_init(ctypes.byref(h), Lx, Ly, float(p), float(q), int(seed)))
+    return Sim(h, Lx, Ly)
+
+
+def okpz_init_on(Lx: int, Ly: int, p: float, q: float, seed: int, dev_ptr: int, nbytes: int,
+                 stream_ptr: int | None) -> "Sim":
+    h = _vp()
+    _check(_lib.okpz_init_on(ctypes.byref(h), Lx, Ly, float(p), float(q), int(seed),
+                             _vp(dev_ptr), nbytes, _vp(stream_ptr or 0)))
+    return Sim(h, Lx, Ly)
+
+
+def okpz_load(buf: bytes) -> "Sim":
+    h = _vp()
+    b = ctypes.create_string_buffer(buf, len(buf))
+    _check(_lib.okpz_load(ctypes.byref(h), b, len(buf)))
+    sim = Sim(h, 0, 0)
+    sim.Ly, sim.Lx = sim._shape_from_lattice_size(buf)
+    return sim
+
+
+class Sim:
+    """One simulated lattice (a handle of the C library)."""
+
+    def __init__(self, handle, Lx: int, Ly: int):
+        self._h = handle
+        self.Lx, self.Ly = Lx, Ly
+        self._keep = None  # caller-owned buffer kept alive with the handle
+
+    @staticmethod
+    def _shape_from_lattice_size(buf: bytes) -> tuple:
+        Lx, Ly = np.frombuffer(buf[16:32], dtype=np.int64)
+        return int(Ly), int(Lx)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sweep(self, n_mcs: int) -> None:
+        _check(_lib.okpz_sweep(self._h, int(n_mcs)))
+
+    def width(self, t: int | None = None) -> tuple:
+        """(sum_h, sum_h2) at MCS t (default: now), exact integers."""
+        if t is None:
+            t = self.time()
+        s1, s2 = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.okpz_width(self._h, int(t), ctypes.byref(s1), ctypes.byref(s2)))
+        return s1.value, s2.value
+
+    def w2(self) -> float:
+        v = ctypes.c_double()
+        _check(_lib.okpz_w2(self._h, ctypes.byref(v)))
+        return v.value
+
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        _check(_lib.okpz_time(self._h, ctypes.byref(t)))
+        return t.value
+
+    def h0(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.okpz_h0(self._h, ctypes.byref(v)))
+        return v.value
+
+    def stream(self) -> int:
+        return _lib.okpz_stream(self._h) or 0
+
+    def get_lattice(self) -> np.ndarray:
+        out = np.empty((self.Ly, self.Lx), dtype=np.uint8)
+        _check(_lib.okpz_get_lattice(self._h, out.ctypes.data_as(_u8p), out.nbytes))
+        return out
+
+    def get_rows(self, y0: int, nrows: int) -> np.ndarray:
+        out = np.empty((nrows, self.Lx), dtype=np.uint8)
+        _check(_lib.okpz_get_rows(self._h, int(y0), int(nrows), out.ctypes.data_as(_u8p),
+                                  out.nbytes))
+        return out
+
+    def set_lattice(self, lat: np.ndarray, H0: int, t: int) -> None:
+        lat = np.ascontiguousarray(lat, dtype=np.uint8)
+        if lat.shape != (self.Ly, self.Lx):
+            raise ValueError(f"lattice shape {lat.shape} != {(self.Ly, self.Lx)}")
+        _check(_lib.okpz_set_lattice(self._h, lat.ctypes.data_as(_u8p), lat.nbytes, int(H0),
+                                     int(t)))
+
+    def save(self) -> bytes:
+        n = _sz(0)
+        _check(_lib.okpz_save(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(_lib.okpz_save(self._h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def sync(self) -> None:
+        _check(_lib.okpz_sync(self._h))
+
+    def free(self) -> None:
+        if self._h:
+            _check(_lib.okpz_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every symbol ``include/okpz.h``
+declares; argument validation that happens before any device call (CPU)."""
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "okpz.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(okpz_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1110_6745_amd import okpz
+
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(okpz.lib(), n), f"{n} not exported"
+    assert sorted(okpz.EXPORTED) == names
+
+
+def test_geometry_matches_oracle():
+    from paper_1110_6745_amd import okpz
+
+    for Lx, Ly in [(32, 32), (96, 64), (256, 256), (320, 192), (4096, 4096), (2**17, 2**17),
+                   (1024, 32)]:
+        assert okpz.okpz_geometry(Lx, Ly) == oracle.geometry(Lx, Ly)
+
+
+def test_required_bytes():
+    from paper_1110_6745_amd import okpz
+
+    # two lattice copies of 2 bits per site + small scratch
+    n = okpz.okpz_required_bytes(2**17, 2**17)
+    assert 2 * 2**34 // 4 <= n < 2 * 2**34 // 4 + 2**22
+    assert okpz.okpz_required_bytes(33, 32) == 0
+
+
+@pytest.mark.parametrize("Lx,Ly,p,q", [(33, 32, 1, 0), (32, 16, 1, 0), (0, 32, 1, 0),
+                                        (2**21, 32, 1, 0), (32, 32, 1.5, 0), (32, 32, 0, -0.1),
+                                        (32, 32, float("nan"), 0)])
+def test_init_rejects_bad_arguments(Lx, Ly, p, q):
+    from paper_1110_6745_amd import okpz
+
+    with pytest.raises(okpz.OkpzError) as e:
+        okpz.okpz_init(Lx, Ly, p, q, 1)
+    assert e.value.code == okpz.OKPZ_EINVAL
