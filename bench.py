@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--L", type=int, default=1 << 17)
+    ap.add_argument("--threads", type=int, default=1024, help="sweep workgroup size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib", action="store_true", help="run a 1 GiB copy first (counters)")
     args = ap.parse_args()
@@ -98,6 +99,7 @@ def main():
     buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     sim = okpz.okpz_init_on(L, L, p, q, seed, buf.data_ptr(), nbytes, stream.cuda_stream)
+    sim.set_threads(args.threads)
 
     sim.sweep(args.warmup)
     torch.cuda.synchronize()
@@ -139,7 +141,7 @@ def main():
         "config": {"workload": f"octahedron model {L}x{L} periodic, flat init, p=1 q=0, seed 1, "
                                f"MCS {t_lo}..{t_hi}, exact W^2 at t_(i+1)=(t_i+10)e^0.01",
                    "Lx": L, "Ly": L, "p": p, "q": q, "seed": seed,
-                   "width_samples": len(widths)},
+                   "width_samples": len(widths), "threads_per_workgroup": args.threads},
         "sweep_kernel_ms": sweep_ms,
         "sweep_site_updates_per_s": N / (sweep_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,

@@ -106,6 +106,12 @@ int okpz_set_lattice(okpz_sim *s, const uint8_t *host, size_t bytes, int64_t H0,
 int okpz_save(okpz_sim *s, void *buf, size_t *bytes);
 int okpz_load(okpz_sim **out, const void *buf, size_t bytes);
 
+/* Execution mapping of the sweep: threads per workgroup (256, 512 or 1024;
+ * default 1024), i.e. 4, 2 or 1 thread cells per thread for 256 x 256 blocks.
+ * The trajectory does not depend on it: every random decision is keyed by
+ * (seed, sweep, block, step, cell), never by thread. */
+int okpz_set_threads(okpz_sim *s, int threads);
+
 /* Wait for the handle's stream. */
 int okpz_sync(okpz_sim *s);
 

@@ -31,6 +31,7 @@ struct okpz_sim {
     bool own_stream;
     void *mem;
     bool own_mem;
+    int threads;  // sweep workgroup size (execution mapping only)
 };
 
 namespace {
@@ -152,6 +153,7 @@ int make_sim(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_
     s->cur = 0;
     s->ox = 0;
     s->t = 0;
+    s->threads = 1024;
     int rc = alloc_state(s, dev_buf, bytes, stream);
     if (rc != OKPZ_OK) {
         delete s;
@@ -382,7 +384,7 @@ int okpz_sweep(okpz_sim *s, int64_t n_mcs)
         a.sx = sx;
         a.sy = sy;
         a.s = sw;
-        HIP_TRY(okpz::launch_sweep(a, s->stream));
+        HIP_TRY(okpz::launch_sweep(a, s->threads, s->stream));
         s->cur ^= 1;
         s->ox = sx;
         s->t += 1;
@@ -555,6 +557,15 @@ int okpz_load(okpz_sim **out, const void *buf, size_t bytes)
     s->ox = h.ox;
     s->t = h.t;
     *out = s;
+    return OKPZ_OK;
+}
+
+int okpz_set_threads(okpz_sim *s, int threads)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    if (!okpz::sweep_threads_ok(threads))
+        return fail(OKPZ_EINVAL, "threads per workgroup must be 256, 512 or 1024");
+    s->threads = threads;
     return OKPZ_OK;
 }
 

@@ -74,7 +74,10 @@ void block_shift(uint32_t k0, uint32_t k1, uint32_t s, const Geometry &g, int32_
                  int32_t *sy);
 
 hipError_t launch_init(uint32_t *planes, int32_t Ly, int32_t W, hipStream_t st);
-hipError_t launch_sweep(const SweepLaunch &a, hipStream_t st);
+// threads per workgroup: 256, 512 or 1024 (execution mapping only; the
+// result does not depend on it)
+hipError_t launch_sweep(const SweepLaunch &a, int threads, hipStream_t st);
+bool sweep_threads_ok(int threads);
 
 // Width: per-row partial sums into `rows` scratch (3 * Ly int64), then one
 // workgroup combines them into out[0..3] = {S1' lo, S1' hi, S2' lo, S2' hi}

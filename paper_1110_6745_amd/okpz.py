@@ -70,13 +70,14 @@ _sig("okpz_get_rows", ctypes.c_int, _vp, _i64, _i64, _u8p, _sz)
 _sig("okpz_set_lattice", ctypes.c_int, _vp, _u8p, _sz, _i64, _i64)
 _sig("okpz_save", ctypes.c_int, _vp, _vp, ctypes.POINTER(_sz))
 _sig("okpz_load", ctypes.c_int, ctypes.POINTER(_vp), _vp, _sz)
+_sig("okpz_set_threads", ctypes.c_int, _vp, ctypes.c_int)
 _sig("okpz_sync", ctypes.c_int, _vp)
 _sig("okpz_free", ctypes.c_int, _vp)
 _sig("okpz_last_error", ctypes.c_char_p)
 
 EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on", "okpz_sweep",
             "okpz_width", "okpz_w2", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
-            "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_sync",
+            "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads", "okpz_sync",
             "okpz_free", "okpz_last_error"]
 
 
@@ -193,6 +194,9 @@ class Sim:
         buf = ctypes.create_string_buffer(n.value)
         _check(_lib.okpz_save(self._h, buf, ctypes.byref(n)))
         return buf.raw[: n.value]
+
+    def set_threads(self, threads: int) -> None:
+        _check(_lib.okpz_set_threads(self._h, int(threads)))
 
     def sync(self) -> None:
         _check(_lib.okpz_sync(self._h))

@@ -161,3 +161,36 @@ def test_init_on_caller_buffer_and_stream(okpz):
     compare(sim, ref, H0, "init_on")
     sim.free()
     del buf
+
+
+@pytest.mark.parametrize("Lx,Ly", [(256, 256), (96, 64), (512, 256)])
+def test_execution_mapping_does_not_change_the_result(okpz, Lx, Ly):
+    """Every workgroup size gives the same bits (the contract keys random
+    decisions by cell, never by thread); also a race detector for the LDS
+    step loop."""
+    ref = oracle.flat(Lx, Ly)
+    H0 = oracle.run(ref, 0.95, 0.05, 6, 0, 4, 0)
+    for threads in (256, 512, 1024):
+        sim = okpz.okpz_init(Lx, Ly, 0.95, 0.05, 6)
+        sim.set_threads(threads)
+        sim.sweep(4)
+        compare(sim, ref, H0, f"threads={threads}")
+        sim.free()
+
+
+@pytest.mark.parametrize("p,q", [inputs.PQ_GROWTH, inputs.PQ_ASYM])
+def test_every_sweep_for_a_hundred_sweeps(okpz, p, q):
+    """One 256 x 256 block, 100 sweeps, lattice and H0 checked after every
+    sweep (the block containing site (0,0) is the whole lattice, so every
+    sweep exercises the H0 bookkeeping)."""
+    Lx = Ly = 256
+    sim = okpz.okpz_init(Lx, Ly, p, q, 1)
+    lat = oracle.flat(Lx, Ly)
+    H0 = 0
+    for s in range(100):
+        sim.sweep(1)
+        H0 = oracle.sweep(lat, p, q, 1, s, H0)
+        assert sim.h0() == H0, f"sweep {s}: H0 {sim.h0()} != {H0}"
+        if s % 10 == 9:
+            assert np.array_equal(sim.get_lattice(), lat), f"sweep {s}: lattice differs"
+    sim.free()
