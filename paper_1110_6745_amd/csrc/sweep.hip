@@ -97,7 +97,12 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a)
         a.By = kFixedB;
     }
     constexpr int kCpt = kCellsMax / kThreads;  // cells per thread at 256x256
-    extern __shared__ __align__(16) uint8_t smem[];
+    // 256 x 256 blocks use a static tile (its base folds into the LDS
+    // instruction offsets); other block sides use dynamic LDS.
+    extern __shared__ __align__(16) uint8_t smem_dyn[];
+    __shared__ __align__(16) uint8_t smem_fix[kFixedB ? (kFixedB + 1) * kFixedB : 16];
+    __shared__ uint32_t opack_lds[kSteps / 2];
+    uint8_t *smem = kFixedB ? smem_fix : smem_dyn;
     const int pitch = a.Bx;
     uint8_t *tile = smem + pitch;                 // one guard row below row 0
 
@@ -111,15 +116,15 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a)
     const int bi = bid % a.nbx, bj = bid / a.nbx;
     const int wpr = a.Bx >> 5;
 
-    // cell origins of the 64 steps: one counter per pair of steps.  Every
-    // wavefront computes them in its lanes 0..31 (lane m: steps 2m, 2m+1,
-    // three bits per coordinate) and reads them back per step with readlane.
-    uint32_t opack;
-    {
-        const uint32_t lane = (uint32_t)(tid & 63);
-        const Ctr4 r = philox10_dev(Ctr4{a.s, (uint32_t)bid, lane & 31u, kTagOrigin}, a.k0, a.k1);
-        opack = (r.x >> 29) | ((r.y >> 29) << 3) | ((r.z >> 29) << 6) | ((r.w >> 29) << 9);
+    // cell origins of the 64 steps: one counter per pair of steps, computed
+    // once per block (thread m: steps 2m, 2m+1, three bits per coordinate);
+    // every thread keeps word (lane mod 32) and reads step k's word back with
+    // readlane.
+    if (tid < kSteps / 2) {
+        const Ctr4 r = philox10_dev(Ctr4{a.s, (uint32_t)bid, (uint32_t)tid, kTagOrigin}, a.k0, a.k1);
+        opack_lds[tid] = (r.x >> 29) | ((r.y >> 29) << 3) | ((r.z >> 29) << 6) | ((r.w >> 29) << 9);
     }
+    // (read after the barrier that ends the load phase)
 
     // ---- HBM -> LDS with periodic wrap, bits -> bytes ---------------------
     const int x0 = (a.sx + bi * a.Bx) % a.Lx;
@@ -156,6 +161,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a)
     }
     __syncthreads();
 
+    const uint32_t opack = opack_lds[tid & 31];
     const bool has00 = (bid == a.blk00);
     int pre00 = 0;
     if (has00) {  // uniform per workgroup
@@ -215,10 +221,14 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a)
                 const uint32_t h16 = (e & 1) ? (sw[j][e >> 1] >> 16) : (sw[j][e >> 1] & 0xffffu);
                 const uint32_t i = __umul24(h16, 49u) >> 16;  // one of the 7x7 active sites
                 const uint32_t bq = __umul24(i, 37u) >> 8;    // i / 7
-                const uint32_t aq = i - 7u * bq;
-                const uint32_t u = (ox + cxo[j] + aq) & mxj[j];
-                const uint32_t v = (oy + cyo[j] + bq) & myj[j];
-                off[j] = __umul24(v, (uint32_t)pitch) + u;  // site byte = smem[off + pitch]
+                const uint32_t ur = ox + cxo[j] + (i - 7u * bq);
+                const uint32_t vr = oy + cyo[j] + bq;
+                if (kFixedB == 256) {
+                    // ((vr mod 256) << 8) | (ur mod 256) in one byte permute
+                    off[j] = __builtin_amdgcn_perm(vr, ur, 0x0C0C0400u);
+                } else {
+                    off[j] = __umul24(vr & myj[j], (uint32_t)pitch) + (ur & mxj[j]);
+                }
                 sv[j] = smem[off[j] + pitch];
                 lv[j] = smem[off[j] + pitch - 1];
                 dv[j] = smem[off[j]];
@@ -227,11 +237,16 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a)
             for (int j = 0; j < kCpt; ++j) {
                 // five-bit code: bits 0-2 from the site, bit 3 from the left
                 // neighbour, bit 4 from the lower neighbour
-                const uint32_t t = (lv[j] & 8u) | (dv[j] & ~8u);
-                const uint32_t code = (t & 24u) | (sv[j] & ~24u);
+                // bitwise mux c ? a : b (truth table 0xE4): bit 3 from l,
+                // bit 4 from d, the others from s
+                const uint32_t t = __builtin_amdgcn_bitop3_b32(lv[j], dv[j], 8u, 0xE4);
+                const uint32_t code = __builtin_amdgcn_bitop3_b32(t, sv[j], 24u, 0xE4);
                 bool flip;
                 if (kMode == kGrowth) {
-                    flip = (code == 3u);
+                    // minimum: the site byte is exactly 0x1B (bx = by = 1 and
+                    // copies, not dead) and neither neighbour bit is set
+                    const uint32_t m = (lv[j] & 8u) | (dv[j] & ~8u);
+                    flip = (((m & 24u) | (sv[j] ^ 0x1Bu)) == 0u);
                 } else if (kMode == kFixed) {
                     flip = (fixed_tbl >> code) & 1u;
                 } else {
@@ -241,7 +256,8 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a)
                     flip = (tbl >> code) & 1u;
                 }
                 if (flip) {
-                    smem[off[j] + pitch] = (uint8_t)(sv[j] ^ 0x1Bu);
+                    // a growth flip only ever turns 0x1B (minimum) into 0
+                    smem[off[j] + pitch] = (kMode == kGrowth) ? (uint8_t)0 : (uint8_t)(sv[j] ^ 0x1Bu);
                     smem[off[j] + pitch - 1] = (uint8_t)(lv[j] ^ 0x09u);
                     smem[off[j]] = (uint8_t)(dv[j] ^ 0x12u);
                 }
@@ -285,9 +301,9 @@ template <int kThreads, int kMode, int kFixedB>
 hipError_t launch_b(const SweepLaunch &a, hipStream_t st)
 {
     const int nblk = a.nbx * a.nby;
-    const size_t lds = (size_t)(a.By + 1) * a.Bx;
+    const size_t lds = kFixedB ? 0 : (size_t)(a.By + 1) * a.Bx;
     static bool attr_set = false;
-    if (!attr_set) {
+    if (!attr_set && !kFixedB) {
         // tiles up to 257 x 256 bytes exceed the 64 KiB default of dynamic LDS
         const int cap = (kMaxB + 1) * kMaxB;
         hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<kThreads, kMode, kFixedB>,
