@@ -1,0 +1,322 @@
+// Device side of one Monte Carlo sweep (Sec. II, Eq. (1)) for a group of
+// device-level blocks of one lattice; shared by the per-lattice sweep kernel
+// and the persistent batch kernel.
+//
+// A workgroup owns G blocks of one sweep (G = 1 for 256 x 256 blocks, more
+// for smaller blocks so that a workgroup always holds about 1024 cells):
+//   1. HBM -> LDS: each block's By rows of Bx sites are cut out of the
+//      periodic lattice at the sweep's random shift (one-site granularity; a
+//      funnel shift of two stored words per 32 sites) and expanded to one byte
+//      per site;
+//   2. C*C = 64 steps in LDS: per step one cell origin per block, one site per
+//      8x8 thread cell, the four-bond test on a five-bit code and, when
+//      accepted, three byte stores;
+//   3. LDS -> HBM: bytes are packed back to bits and each block is written
+//      *aligned* into the other lattice copy, whose stored columns start at
+//      this sweep's shift.  No two workgroups write the same word, so the
+//      store needs no atomics and the shift keeps one-site granularity.
+//
+// LDS byte of a site: bit 0 = bx (sigma_x = +1), bit 1 = by, bit 2 = block
+// border (dead) marker, bit 3 = copy of bx, bit 4 = copy of by.  For the site
+// s, its left neighbour l and lower neighbour d, the five-bit code
+//   k = (s & 7) | (l & 8) | (d & 16)
+// holds bx(u,v), by(u,v), dead(u,v), bx(u-1,v), by(u,v-1).  k = 3 is a local
+// minimum (-1 +1; -1 +1), k = 24 a local maximum; a dead site never matches.
+// An accepted move rewrites the three bytes (s ^ 0x1B, l ^ 0x09, d ^ 0x12).
+// Within a step no other lane reads or writes those bytes (sites attempted
+// together are never nearest or diagonal neighbours: each 8x8 cell has a dead
+// row and column), so plain byte stores suffice.
+//
+// The height of site (0,0) is tracked without touching the attempt loop: the
+// block containing it compares the sigma_x count of its row prefix before and
+// after the steps (the row's block-border site never moves).
+#pragma once
+
+#include "okpz_internal.h"
+
+namespace okpz {
+namespace core {
+
+constexpr int kMaxB = 256;
+constexpr int kCellsMax = (kMaxB / 8) * (kMaxB / 8);  // cells a workgroup holds
+constexpr int kSteps = 64;                             // C*C with C = 8
+constexpr int kMaxGroup = 64;                          // blocks per group (32 x 32)
+// LDS of a group: G tiles of (By + 1) x Bx bytes (one guard row each) with
+// G * Bx * By = 65536, plus 32 origin words per block.
+constexpr int kGroupLds = 65536 + kMaxGroup * 32 + kMaxGroup * 32 * 4;
+
+// Acceptance modes: p = 1, q = 0 (pure growth); p and q each 0 or 1;
+// general p, q (per-attempt acceptance draws).
+enum Mode : int { kGrowth = 0, kFixed = 1, kDraw = 2 };
+
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
+{
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// Philox4x32-10 with the three-input XORs as single bit operations.
+__device__ __forceinline__ Ctr4 philox10_dev(Ctr4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t n0 = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), c.y, k0, 0x96);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), c.w, k1, 0x96);
+        c = Ctr4{n0, (uint32_t)m1, n2, (uint32_t)m0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 4 bits -> 4 bytes (bit j to bit 0 of byte j)
+__device__ __forceinline__ uint32_t spread4(uint32_t nib)
+{
+    return __umul24(nib, 0x204081u) & 0x01010101u;
+}
+
+// 4 bytes with values in bit 0 -> 4 bits, scaled by `w` (byte weights)
+__device__ __forceinline__ uint32_t gather4(uint32_t bytes01, uint32_t w, uint32_t acc)
+{
+    return __builtin_amdgcn_udot4(bytes01, w, acc, false);
+}
+
+__device__ __forceinline__ int row_prefix_bx(const uint8_t *row, int n)
+{
+    int c = 0;
+    for (int u = 0; u < n; ++u) c += row[u] & 1;
+    return c;
+}
+
+__device__ __forceinline__ int ilog2(uint32_t v) { return 31 - __builtin_clz(v); }
+
+// Blocks per group for a block size: about 1024 cells per workgroup.
+__host__ __device__ inline int group_size(int Bx, int By, int nblk)
+{
+    const int cpb = (Bx / 8) * (By / 8);
+    int g = kCellsMax / cpb;
+    if (g > kMaxGroup) g = kMaxGroup;
+    if (g > nblk) g = nblk;
+    return g < 1 ? 1 : g;
+}
+
+// One sweep of blocks [b0, b0 + G) of the lattice described by `a`.
+//   kFixedB = 256: 256 x 256 blocks, G = 1, static geometry (the three LDS
+//                  addresses of an attempt are one register plus offsets);
+//   kFixedB = 0:   any block sides 32..256, geometry from `a`.
+// smem: at least G * (By + 1) * Bx bytes; opk: G * 32 words of LDS.
+template <int kThreads, int kMode, int kFixedB>
+__device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const int G,
+                                            uint8_t *__restrict__ smem, uint32_t *opk)
+{
+    constexpr bool kDrawAccept = (kMode == kDraw);
+    constexpr int kCpt = kCellsMax / kThreads;
+    if (kFixedB) {
+        a.Bx = kFixedB;
+        a.By = kFixedB;
+    }
+    const int tid = threadIdx.x;
+    const int Bx = a.Bx, By = a.By;
+    const int wpr = Bx >> 5;
+    const int tsz = (By + 1) * Bx;  // bytes per tile incl. guard row
+    const int lcpb = ilog2((uint32_t)((Bx >> 3) * (By >> 3)));
+    const int ncx = Bx >> 3;
+
+    // cell origins: one counter per pair of steps and block; word m of block
+    // g holds steps 2m and 2m+1 (three bits per coordinate).
+    for (int e = tid; e < G * (kSteps / 2); e += kThreads) {
+        const int g = e >> 5, m = e & 31;
+        const Ctr4 r = philox10_dev(Ctr4{a.s, (uint32_t)(b0 + g), (uint32_t)m, kTagOrigin}, a.k0,
+                                    a.k1);
+        opk[e] = (r.x >> 29) | ((r.y >> 29) << 3) | ((r.z >> 29) << 6) | ((r.w >> 29) << 9);
+    }
+
+    // ---- HBM -> LDS with periodic wrap, bits -> bytes ---------------------
+    for (int e = tid; e < G * By * wpr; e += kThreads) {
+        const int k = e % wpr;
+        const int rest = e / wpr;
+        const int v = rest % By;
+        const int g = rest / By;
+        const int bid = b0 + g;
+        const int bi = bid % a.nbx, bj = bid / a.nbx;
+        const int x0 = (a.sx + bi * Bx) % a.Lx;
+        const int xs = (x0 - a.ox_src + a.Lx) % a.Lx;
+        int y = a.sy + bj * By + v;
+        if (y >= a.Ly) y -= a.Ly;
+        int gw = (xs >> 5) + k;
+        if (gw >= a.W) gw -= a.W;
+        int gw1 = gw + 1;
+        if (gw1 == a.W) gw1 = 0;
+        const uint32_t off = (uint32_t)(xs & 31);
+        const uint32_t *r0 = a.src + (size_t)y * a.W;
+        const uint32_t *r1 = a.src + ((size_t)a.Ly + y) * a.W;
+        const uint32_t bxw = funnel(r0[gw1], r0[gw], off);
+        const uint32_t byw = funnel(r1[gw1], r1[gw], off);
+        const uint32_t dead = (v == 0) ? 0x04040404u : 0u;
+        uint32_t d[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const uint32_t sx = spread4((bxw >> (4 * m)) & 15u);
+            const uint32_t sy = spread4((byw >> (4 * m)) & 15u);
+            const uint32_t sxy = sx + (sy << 1);  // bx in bit 0, by in bit 1
+            d[m] = sxy + (sxy << 3) + dead;        // copies in bits 3 and 4
+        }
+        if (k == 0) d[0] |= 4u;  // column u = 0 is the block border
+        uint4 *dst = reinterpret_cast<uint4 *>(smem + g * tsz + (v + 1) * Bx + 32 * k);
+        dst[0] = uint4{d[0], d[1], d[2], d[3]};
+        dst[1] = uint4{d[4], d[5], d[6], d[7]};
+    }
+    __syncthreads();
+
+    // H0: the block holding lattice site (0,0), if it is in this group
+    const int g00 = a.blk00 - b0;
+    const bool has00 = (g00 >= 0 && g00 < G);  // uniform per workgroup
+    int pre00 = 0;
+    if (has00) {
+        if (tid == 0) pre00 = row_prefix_bx(smem + g00 * tsz + (a.v00 + 1) * Bx, a.u00);
+        __syncthreads();  // no step may flip that row before it is counted
+    }
+
+    // ---- the thread's cells ----------------------------------------------
+    // A cell beyond the group gets zero masks and tile 0, so its site is
+    // always (0,0) of block 0, a dead-border site: its attempt is a no-op.
+    const bool wave_in_block = lcpb >= 6;  // 64 lanes of a wave share a block
+    uint32_t cxo[kCpt], cyo[kCpt], mxj[kCpt], myj[kCpt], gbase[kCpt], cid[kCpt], bidj[kCpt];
+    uint32_t gj[kCpt];
+    uint32_t opreg[kCpt];
+#pragma unroll
+    for (int j = 0; j < kCpt; ++j) {
+        const int q = tid + j * kThreads;
+        const int g = q >> lcpb;
+        const int c = q & ((1 << lcpb) - 1);
+        const bool live = g < G;
+        cid[j] = (uint32_t)c;
+        bidj[j] = (uint32_t)(b0 + (live ? g : 0));
+        cxo[j] = (uint32_t)((c % ncx) * 8 + 1);
+        cyo[j] = (uint32_t)((c / ncx) * 8 + 1);
+        mxj[j] = live ? (uint32_t)Bx - 1u : 0u;
+        myj[j] = live ? (uint32_t)By - 1u : 0u;
+        gbase[j] = live ? (uint32_t)(g * tsz) : 0u;
+        gj[j] = live ? (uint32_t)g : 0u;
+        opreg[j] = opk[(live ? g : 0) * 32 + (tid & 31)];
+    }
+    const uint32_t fixed_tbl = (a.Tp != 0 ? (1u << 3) : 0u) | (a.Tq != 0 ? (1u << 24) : 0u);
+    (void)fixed_tbl;
+
+    for (int gs = 0; gs < kSteps / 8; ++gs) {
+        uint32_t sw[kCpt][4];
+#pragma unroll
+        for (int j = 0; j < kCpt; ++j) {
+            const Ctr4 r = philox10_dev(Ctr4{a.s, bidj[j], ((uint32_t)gs << 16) | cid[j], kTagSite},
+                                        a.k0, a.k1);
+            sw[j][0] = r.x; sw[j][1] = r.y; sw[j][2] = r.z; sw[j][3] = r.w;
+        }
+        uint32_t aw[kCpt][4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = gs * 8 + e;
+            if (kDrawAccept && (e & 3) == 0) {
+#pragma unroll
+                for (int j = 0; j < kCpt; ++j) {
+                    const Ctr4 r = philox10_dev(
+                        Ctr4{a.s, bidj[j], ((uint32_t)(k >> 2) << 16) | cid[j], kTagAccept}, a.k0,
+                        a.k1);
+                    aw[j][0] = r.x; aw[j][1] = r.y; aw[j][2] = r.z; aw[j][3] = r.w;
+                }
+            }
+            // all reads of the step first: the cells' byte sets are disjoint
+            uint32_t off[kCpt], sv[kCpt], lv[kCpt], dv[kCpt];
+#pragma unroll
+            for (int j = 0; j < kCpt; ++j) {
+                uint32_t op;
+                if (kFixedB || wave_in_block)
+                    op = (uint32_t)__builtin_amdgcn_readlane((int)opreg[j], k >> 1);
+                else
+                    op = opk[(gj[j] << 5) + (k >> 1)];
+                op >>= 6 * (e & 1);
+                const uint32_t ox = op & 7u, oy = (op >> 3) & 7u;
+                const uint32_t h16 = (e & 1) ? (sw[j][e >> 1] >> 16) : (sw[j][e >> 1] & 0xffffu);
+                const uint32_t i = __umul24(h16, 49u) >> 16;  // one of the 7x7 active sites
+                const uint32_t bq = __umul24(i, 37u) >> 8;    // i / 7
+                const uint32_t ur = ox + cxo[j] + (i - 7u * bq);
+                const uint32_t vr = oy + cyo[j] + bq;
+                if (kFixedB == 256) {
+                    // ((vr mod 256) << 8) | (ur mod 256) in one byte permute
+                    off[j] = __builtin_amdgcn_perm(vr, ur, 0x0C0C0400u);
+                } else {
+                    off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
+                }
+                sv[j] = smem[off[j] + Bx];
+                lv[j] = smem[off[j] + Bx - 1];
+                dv[j] = smem[off[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < kCpt; ++j) {
+                bool flip;
+                if (kMode == kGrowth) {
+                    // minimum: the site byte is exactly 0x1B (bx = by = 1 and
+                    // copies, not dead) and neither neighbour bit is set
+                    const uint32_t m = (lv[j] & 8u) | (dv[j] & ~8u);
+                    flip = (((m & 24u) | (sv[j] ^ 0x1Bu)) == 0u);
+                } else {
+                    // bitwise mux c ? a : b (truth table 0xE4): bit 3 from l,
+                    // bit 4 from d, the others from s
+                    const uint32_t t = __builtin_amdgcn_bitop3_b32(lv[j], dv[j], 8u, 0xE4);
+                    const uint32_t code = __builtin_amdgcn_bitop3_b32(t, sv[j], 24u, 0xE4);
+                    uint32_t tbl = fixed_tbl;
+                    if (kDrawAccept) {
+                        const uint32_t r = aw[j][e & 3];
+                        tbl = ((uint64_t)r < a.Tp ? (1u << 3) : 0u) |
+                              ((uint64_t)r < a.Tq ? (1u << 24) : 0u);
+                    }
+                    flip = (tbl >> code) & 1u;
+                }
+                if (flip) {
+                    // a growth flip only ever turns 0x1B (minimum) into 0
+                    smem[off[j] + Bx] = (kMode == kGrowth) ? (uint8_t)0 : (uint8_t)(sv[j] ^ 0x1Bu);
+                    smem[off[j] + Bx - 1] = (uint8_t)(lv[j] ^ 0x09u);
+                    smem[off[j]] = (uint8_t)(dv[j] ^ 0x12u);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    if (has00 && tid == 0) {
+        const int post00 = row_prefix_bx(smem + g00 * tsz + (a.v00 + 1) * Bx, a.u00);
+        *a.h0 += 2 * (int64_t)(post00 - pre00);
+    }
+
+    // ---- LDS -> HBM: bytes -> bits, aligned into the other copy -----------
+    for (int e = tid; e < G * By * wpr; e += kThreads) {
+        const int k = e % wpr;
+        const int rest = e / wpr;
+        const int v = rest % By;
+        const int g = rest / By;
+        const int bid = b0 + g;
+        const int bi = bid % a.nbx, bj = bid / a.nbx;
+        int y = a.sy + bj * By + v;
+        if (y >= a.Ly) y -= a.Ly;
+        const uint4 *src = reinterpret_cast<const uint4 *>(smem + g * tsz + (v + 1) * Bx + 32 * k);
+        const uint4 q0 = src[0], q1 = src[1];
+        const uint32_t d[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        uint32_t bxw = 0, byw = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {  // byte b of the word: sites 8b .. 8b+7
+            const uint32_t lo = d[2 * b], hi = d[2 * b + 1];
+            const uint32_t xb = gather4(hi & 0x01010101u, 0x80402010u,
+                                        gather4(lo & 0x01010101u, 0x08040201u, 0u));
+            const uint32_t yb = gather4((hi >> 1) & 0x01010101u, 0x80402010u,
+                                        gather4((lo >> 1) & 0x01010101u, 0x08040201u, 0u));
+            bxw |= xb << (8 * b);
+            byw |= yb << (8 * b);
+        }
+        const size_t col = (size_t)bi * wpr + k;
+        a.dst[(size_t)y * a.W + col] = bxw;
+        a.dst[((size_t)a.Ly + y) * a.W + col] = byw;
+    }
+}
+
+}  // namespace core
+}  // namespace okpz

@@ -17,7 +17,8 @@ PQ_LIST = [PQ_GROWTH, PQ_ASYM, PQ_SYM, (0.3, 0.8), (0.0, 1.0), (0.0, 0.0)]
 # lattice shapes: square powers of two, ragged block sizes (power-of-two
 # divisor below 256), rectangles
 SHAPES_SMALL = [(4, 4), (8, 8), (12, 20), (32, 32), (96, 64), (64, 160)]
-SHAPES_GPU = [(32, 32), (64, 32), (96, 96), (256, 256), (320, 192), (512, 1024)]
+SHAPES_GPU = [(32, 32), (64, 32), (96, 96), (256, 256), (320, 192), (512, 1024), (1056, 96),
+              (2080, 64), (128, 640)]
 
 
 def rough_state(Lx, Ly, seed, mcs=3, p=0.7, q=0.4):

@@ -42,7 +42,7 @@ def test_flat_state(okpz):
         sim.free()
 
 
-@pytest.mark.parametrize("Lx,Ly", inputs.SHAPES_GPU[:5])
+@pytest.mark.parametrize("Lx,Ly", inputs.SHAPES_GPU)
 @pytest.mark.parametrize("p,q", inputs.PQ_LIST[:5])
 def test_sweeps_match_oracle(okpz, Lx, Ly, p, q):
     seed = 1 + Lx + 7 * Ly
@@ -163,7 +163,7 @@ def test_init_on_caller_buffer_and_stream(okpz):
     del buf
 
 
-@pytest.mark.parametrize("Lx,Ly", [(256, 256), (96, 64), (512, 256)])
+@pytest.mark.parametrize("Lx,Ly", [(256, 256), (96, 64), (512, 256), (1056, 96), (2080, 64)])
 def test_execution_mapping_does_not_change_the_result(okpz, Lx, Ly):
     """Every workgroup size gives the same bits (the contract keys random
     decisions by cell, never by thread); also a race detector for the LDS
