@@ -121,6 +121,60 @@ int okpz_free(okpz_sim *s);
 /* Message of the last error on this thread ("" if none). */
 const char *okpz_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles: many independent realizations of uneven size, each with
+ * its own p, q, seed and length, run to completion in one persistent launch
+ * (the paper's ensembles of independent runs, Sec. III and IV).  Each job
+ * starts from the flat state and records the exact width sums at the
+ * sampling times t_{i+1} = (t_i + 10) e^m (Sec. III; rounded up, duplicates
+ * dropped) and at t_max.  A job's trajectory is bit for bit the one the same
+ * job gives alone through okpz_init/okpz_sweep.
+ * ---------------------------------------------------------------------- */
+typedef struct okpz_job {
+    int64_t Lx, Ly;   /* multiples of 32 in [32, 8192] */
+    double p, q;      /* attachment / detachment probabilities in [0,1] */
+    uint64_t seed;
+    int64_t t_max;    /* MCS to run, 0 <= t_max < 2^31 */
+} okpz_job;
+
+typedef struct okpz_batch okpz_batch; /* opaque */
+
+/* Validate the jobs (OKPZ_EINVAL on a bad job, sampling exponent m outside
+ * (0, 10], or more than 65535 jobs) and allocate every job's lattices and
+ * sample buffers on the device. */
+int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, double m);
+
+/* Execution mapping of the persistent launch: threads per workgroup (256,
+ * 512, 1024) and resident workgroups (0 = two per compute unit).  Results do
+ * not depend on it. */
+int okpz_batch_set_mapping(okpz_batch *b, int32_t threads, int32_t workgroups);
+int okpz_batch_get_mapping(okpz_batch *b, int32_t *threads, int32_t *workgroups);
+
+/* Pick the mapping by timing every candidate on a bounded trial (all jobs
+ * capped at trial_mcs sweeps, results discarded); keeps the fastest. */
+int okpz_batch_autotune(okpz_batch *b, int64_t trial_mcs, int32_t *threads, int32_t *workgroups);
+
+/* Run every job from the flat state to its t_max in one persistent launch.
+ * Synchronous.  OKPZ_EDEVICE if the launch's no-progress watchdog fired. */
+int okpz_batch_run(okpz_batch *b);
+
+/* Device time of the last okpz_batch_run, in milliseconds. */
+int okpz_batch_last_ms(okpz_batch *b, float *ms);
+
+/* Samples of one job after a run: count always; with non-NULL arrays of
+ * capacity cap, the sampling times t, and exact sum_h, sum_h2 (Eq. (Wdef)). */
+int okpz_batch_samples(okpz_batch *b, int32_t job, int64_t *t, int64_t *sum_h, int64_t *sum_h2,
+                       int32_t cap, int32_t *count);
+
+/* Final state of one job: canonical lattice (bytes >= Lx*Ly) and H0. */
+int okpz_batch_get_lattice(okpz_batch *b, int32_t job, uint8_t *host, size_t bytes);
+int okpz_batch_h0(okpz_batch *b, int32_t job, int64_t *h0);
+
+int okpz_batch_free(okpz_batch *b);
+
+/* Message of the last batch error on this thread. */
+const char *okpz_batch_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,127 @@
+// Device side of the exact squared width (Sec. I height reconstruction,
+// Eq. (Wdef)); shared by the per-lattice width kernels and the persistent
+// batch kernel.
+//
+// h(x,y) = H0 + G(y) + P_y(x), with G(y) = sum_{k<y} sigma_y(0,k) and
+// P_y(x) = sum_{l<x} sigma_x(l,y).  width_row: one wavefront reads row y's
+// words once, coalesced, re-aligned to physical columns with a funnel shift;
+// each lane turns its word into a popcount, a wavefront prefix scan gives
+// every word's starting height, and the lane accumulates the word's exact
+// sum and sum of squares.  width_combine: one workgroup scans the column-0
+// sigma_y bits to get G(y) and combines the rows into 128-bit
+// S1' = sum (h - H0) and S2' = sum (h - H0)^2.
+#pragma once
+
+#include "okpz_internal.h"
+
+namespace okpz {
+namespace core {
+
+// Row y of lattice view v by one wavefront (lane = threadIdx.x & 63); lane 0
+// writes rows[y] = sum_x P, rows[Ly + y] = sum_x P^2, rows[2 Ly + y] = the
+// sigma_y bit at physical column 0.
+__device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane, int64_t *rows)
+{
+    const uint32_t *row = v.planes + (size_t)y * v.W;
+    const int xs0 = (v.Lx - v.ox) % v.Lx;  // stored column of physical column 0
+    const uint32_t off = (uint32_t)(xs0 & 31);
+    const int gws = xs0 >> 5;
+
+    int64_t a1 = 0, a2 = 0;
+    int32_t carry = 0;
+    for (int base = 0; base < v.W; base += 64) {
+        const int k = base + lane;
+        uint32_t word = 0;
+        int32_t d = 0;
+        if (k < v.W) {
+            int gw = gws + k;
+            if (gw >= v.W) gw -= v.W;
+            int gw1 = gw + 1;
+            if (gw1 == v.W) gw1 = 0;
+            word = __builtin_amdgcn_alignbit(row[gw1], row[gw], off);
+            d = 2 * __popc(word) - 32;
+        }
+        int32_t incl = d;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        const int32_t base_h = carry + incl - d;  // P_y at the word's first site
+        if (k < v.W) {
+            int32_t q = 0, s1 = 0, s2 = 0;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                s1 += q;
+                s2 += q * q;
+                q += (int32_t)((word >> i) & 1u) * 2 - 1;
+            }
+            const int64_t b = base_h;
+            a1 += 32 * b + s1;
+            a2 += 32 * b * b + 2 * b * s1 + s2;
+        }
+        carry += __shfl(incl, 63, 64);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a1 += __shfl_down(a1, o, 64);
+        a2 += __shfl_down(a2, o, 64);
+    }
+    if (lane == 0) {
+        const uint32_t *rowy = v.planes + ((size_t)v.Ly + y) * v.W;
+        const uint32_t cb = (rowy[xs0 >> 5] >> (xs0 & 31)) & 1u;
+        rows[y] = a1;
+        rows[(size_t)v.Ly + y] = a2;
+        rows[2 * (size_t)v.Ly + y] = (int64_t)cb;
+    }
+}
+
+// Combine the rows into out[0..3] = {S1' lo, S1' hi, S2' lo, S2' hi} (128-bit
+// two's complement halves) with one workgroup of nthreads <= 1024 threads.
+// scan/r1/r2: LDS scratch of nthreads entries each.  Ends with a barrier.
+__device__ __forceinline__ void width_combine(const int64_t *rows, int32_t Lx, int32_t Ly,
+                                              int64_t *out, int32_t *scan, int64_t *r1,
+                                              int64_t *r2)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int per = (Ly + nth - 1) / nth;
+    const int ya = min(Ly, tid * per), yb = min(Ly, ya + per);
+    const int64_t *rs1 = rows, *rs2 = rows + Ly, *col = rows + 2 * (size_t)Ly;
+
+    int32_t local = 0;
+    for (int y = ya; y < yb; ++y) local += 2 * (int32_t)col[y] - 1;
+    scan[tid] = local;
+    __syncthreads();
+    for (int o = 1; o < nth; o <<= 1) {
+        const int32_t t = tid >= o ? scan[tid - o] : 0;
+        __syncthreads();
+        scan[tid] += t;
+        __syncthreads();
+    }
+    int64_t G = scan[tid] - local;  // sum of sigma_y(0,k) for k < ya
+    int64_t s1 = 0, s2 = 0;
+    for (int y = ya; y < yb; ++y) {
+        const int64_t p1 = rs1[y], p2 = rs2[y];
+        s1 += (int64_t)Lx * G + p1;
+        s2 += (int64_t)Lx * G * G + 2 * G * p1 + p2;
+        G += 2 * col[y] - 1;
+    }
+    r1[tid] = s1;
+    r2[tid] = s2;
+    __syncthreads();
+    if (tid == 0) {
+        __int128 t1 = 0, t2 = 0;
+        for (int i = 0; i < nth; ++i) {
+            t1 += r1[i];
+            t2 += r2[i];
+        }
+        out[0] = (int64_t)(uint64_t)t1;
+        out[1] = (int64_t)(t1 >> 64);
+        out[2] = (int64_t)(uint64_t)t2;
+        out[3] = (int64_t)(t2 >> 64);
+    }
+    __syncthreads();
+}
+
+}  // namespace core
+}  // namespace okpz

@@ -75,10 +75,33 @@ _sig("okpz_sync", ctypes.c_int, _vp)
 _sig("okpz_free", ctypes.c_int, _vp)
 _sig("okpz_last_error", ctypes.c_char_p)
 
+class OkpzJob(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int64), ("Ly", ctypes.c_int64), ("p", ctypes.c_double),
+                ("q", ctypes.c_double), ("seed", ctypes.c_uint64), ("t_max", ctypes.c_int64)]
+
+
+_jobp = ctypes.POINTER(OkpzJob)
+_sig("okpz_batch_create", ctypes.c_int, ctypes.POINTER(_vp), _jobp, ctypes.c_int32,
+     ctypes.c_double)
+_sig("okpz_batch_set_mapping", ctypes.c_int, _vp, ctypes.c_int32, ctypes.c_int32)
+_sig("okpz_batch_get_mapping", ctypes.c_int, _vp, _i32p, _i32p)
+_sig("okpz_batch_autotune", ctypes.c_int, _vp, _i64, _i32p, _i32p)
+_sig("okpz_batch_run", ctypes.c_int, _vp)
+_sig("okpz_batch_last_ms", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_float))
+_sig("okpz_batch_samples", ctypes.c_int, _vp, ctypes.c_int32, _i64p, _i64p, _i64p,
+     ctypes.c_int32, _i32p)
+_sig("okpz_batch_get_lattice", ctypes.c_int, _vp, ctypes.c_int32, _u8p, _sz)
+_sig("okpz_batch_h0", ctypes.c_int, _vp, ctypes.c_int32, _i64p)
+_sig("okpz_batch_free", ctypes.c_int, _vp)
+_sig("okpz_batch_last_error", ctypes.c_char_p)
+
 EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on", "okpz_sweep",
             "okpz_width", "okpz_w2", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
             "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads", "okpz_sync",
-            "okpz_free", "okpz_last_error"]
+            "okpz_free", "okpz_last_error", "okpz_batch_create", "okpz_batch_set_mapping",
+            "okpz_batch_get_mapping", "okpz_batch_autotune", "okpz_batch_run",
+            "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
+            "okpz_batch_free", "okpz_batch_last_error"]
 
 
 def _check(rc: int) -> None:
@@ -211,3 +234,96 @@ class Sim:
             self.free()
         except Exception:
             pass
+
+
+def _bcheck(rc: int) -> None:
+    if rc != OKPZ_OK:
+        raise OkpzError(rc, _lib.okpz_batch_last_error().decode(errors="replace"))
+
+
+class Batch:
+    """Many independent realizations run in one persistent launch.
+
+    ``jobs``: iterable of (Lx, Ly, p, q, seed, t_max); ``m``: exponent of the
+    sampling times t_{i+1} = (t_i + 10) e^m.
+    """
+
+    def __init__(self, jobs, m: float = 0.01):
+        arr = (OkpzJob * len(jobs))()
+        for i, (Lx, Ly, p, q, seed, t_max) in enumerate(jobs):
+            arr[i] = OkpzJob(int(Lx), int(Ly), float(p), float(q), int(seed), int(t_max))
+        self.jobs = [tuple(j) for j in jobs]
+        h = _vp()
+        _bcheck(_lib.okpz_batch_create(ctypes.byref(h), arr, len(jobs), float(m)))
+        self._h = h
+
+    def set_mapping(self, threads: int, workgroups: int = 0) -> None:
+        _bcheck(_lib.okpz_batch_set_mapping(self._h, int(threads), int(workgroups)))
+
+    def mapping(self) -> tuple:
+        t, w = ctypes.c_int32(), ctypes.c_int32()
+        _bcheck(_lib.okpz_batch_get_mapping(self._h, ctypes.byref(t), ctypes.byref(w)))
+        return t.value, w.value
+
+    def autotune(self, trial_mcs: int) -> tuple:
+        t, w = ctypes.c_int32(), ctypes.c_int32()
+        _bcheck(_lib.okpz_batch_autotune(self._h, int(trial_mcs), ctypes.byref(t),
+                                         ctypes.byref(w)))
+        return t.value, w.value
+
+    def run(self) -> float:
+        """Run all jobs to t_max; returns the device time in ms."""
+        _bcheck(_lib.okpz_batch_run(self._h))
+        ms = ctypes.c_float()
+        _bcheck(_lib.okpz_batch_last_ms(self._h, ctypes.byref(ms)))
+        return ms.value
+
+    def samples(self, job: int):
+        n = ctypes.c_int32()
+        _bcheck(_lib.okpz_batch_samples(self._h, job, None, None, None, 0, ctypes.byref(n)))
+        t = np.zeros(n.value, dtype=np.int64)
+        s1 = np.zeros(n.value, dtype=np.int64)
+        s2 = np.zeros(n.value, dtype=np.int64)
+        _bcheck(_lib.okpz_batch_samples(self._h, job, t.ctypes.data_as(_i64p),
+                                        s1.ctypes.data_as(_i64p), s2.ctypes.data_as(_i64p),
+                                        n.value, ctypes.byref(n)))
+        return t, s1, s2
+
+    def get_lattice(self, job: int) -> np.ndarray:
+        Lx, Ly = self.jobs[job][0], self.jobs[job][1]
+        out = np.empty((Ly, Lx), dtype=np.uint8)
+        _bcheck(_lib.okpz_batch_get_lattice(self._h, job, out.ctypes.data_as(_u8p), out.nbytes))
+        return out
+
+    def h0(self, job: int) -> int:
+        v = ctypes.c_int64()
+        _bcheck(_lib.okpz_batch_h0(self._h, job, ctypes.byref(v)))
+        return v.value
+
+    def free(self) -> None:
+        if self._h:
+            _bcheck(_lib.okpz_batch_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sampling_times(t_max: int, m: float) -> list:
+    """ceil of t_{i+1} = (t_i + 10) e^m, t_0 = 0, duplicates dropped, plus t_max."""
+    import math
+
+    out, t = [], 0.0
+    while True:
+        t = (t + 10.0) * math.exp(m)
+        if t > t_max:
+            break
+        c = int(math.ceil(t))
+        if not out or out[-1] != c:
+            out.append(c)
+    if t_max > 0 and (not out or out[-1] != t_max):
+        out.append(int(t_max))
+    return out

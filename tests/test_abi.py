@@ -52,3 +52,23 @@ def test_init_rejects_bad_arguments(Lx, Ly, p, q):
     with pytest.raises(okpz.OkpzError) as e:
         okpz.okpz_init(Lx, Ly, p, q, 1)
     assert e.value.code == okpz.OKPZ_EINVAL
+
+
+@pytest.mark.parametrize("job,m", [((33, 32, 1, 0, 1, 5), 0.01), ((32, 32, 1.2, 0, 1, 5), 0.01),
+                                   ((32, 32, 1, 0, 1, -1), 0.01), ((32, 32, 1, 0, 1, 5), 0.0),
+                                   ((16384, 32, 1, 0, 1, 5), 0.01)])
+def test_batch_rejects_bad_jobs(job, m):
+    from paper_1110_6745_amd import okpz
+
+    with pytest.raises(okpz.OkpzError) as e:
+        okpz.Batch([job], m)
+    assert e.value.code == okpz.OKPZ_EINVAL
+
+
+def test_sampling_times_follow_the_paper_recurrence():
+    from paper_1110_6745_amd import okpz
+
+    # t_{i+1} = (t_i + 10) e^m from t_0 = 0 (Sec. III), rounded up
+    assert okpz.sampling_times(100, 0.01)[:4] == [11, 21, 31, 42]
+    assert okpz.sampling_times(100, 0.01)[-1] == 100
+    assert okpz.sampling_times(0, 0.01) == []

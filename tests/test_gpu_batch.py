@@ -1,0 +1,108 @@
+"""Batched ensembles (one persistent launch) against the same jobs run alone.
+
+Every job of a batch must give bit for bit the trajectory it gives alone
+through okpz_init/okpz_sweep (itself pinned to the oracle): the same exact
+width sums at every sampling time, the same final lattice and H0, for any
+execution mapping of the persistent launch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+MIXED = [  # (Lx, Ly, p, q, seed, t_max)
+    (32, 32, 1.0, 0.0, 11, 9), (64, 64, 0.95, 0.05, 12, 13), (96, 96, 1.0, 0.0, 13, 7),
+    (128, 64, 0.3, 0.8, 14, 10), (256, 256, 1.0, 0.0, 15, 12), (320, 192, 0.5, 0.5, 16, 6),
+    (512, 512, 1.0, 0.0, 17, 5), (1056, 96, 0.95, 0.05, 18, 4), (32, 32, 0.0, 0.0, 19, 3),
+    (64, 32, 1.0, 0.0, 20, 0), (2080, 64, 1.0, 1.0, 21, 5),
+]
+M = 0.3
+
+
+@pytest.fixture(scope="module")
+def okpz():
+    from paper_1110_6745_amd import okpz as m
+
+    return m
+
+
+def alone(okpz, job, m):
+    Lx, Ly, p, q, seed, t_max = job
+    sim = okpz.okpz_init(Lx, Ly, p, q, seed)
+    out = []
+    for t in okpz.sampling_times(t_max, m):
+        out.append((t,) + sim.width(t))
+    lat, h0 = sim.get_lattice(), sim.h0()
+    sim.free()
+    return out, lat, h0
+
+
+def check_batch(okpz, b, jobs, m, refs):
+    for r, job in enumerate(jobs):
+        t, s1, s2 = b.samples(r)
+        ref, lat, h0 = refs[r]
+        got = list(zip(t.tolist(), s1.tolist(), s2.tolist()))
+        assert got == ref, f"job {r} {job}: samples differ"
+        assert np.array_equal(b.get_lattice(r), lat), f"job {r} {job}: lattice differs"
+        assert b.h0(r) == h0, f"job {r} {job}: H0 differs"
+
+
+def test_batch_matches_jobs_run_alone(okpz):
+    refs = [alone(okpz, j, M) for j in MIXED]
+    b = okpz.Batch(MIXED, M)
+    b.run()
+    check_batch(okpz, b, MIXED, M, refs)
+    b.free()
+
+
+def test_batch_small_jobs_match_oracle(okpz):
+    jobs = [(32, 32, 1.0, 0.0, 5, 12), (64, 96, 0.95, 0.05, 6, 8)]
+    b = okpz.Batch(jobs, M)
+    b.run()
+    for r, (Lx, Ly, p, q, seed, t_max) in enumerate(jobs):
+        lat = oracle.flat(Lx, Ly)
+        H0 = oracle.run(lat, p, q, seed, 0, t_max, 0)
+        assert np.array_equal(b.get_lattice(r), lat) and b.h0(r) == H0
+        t, s1, s2 = b.samples(r)
+        assert t[-1] == t_max and (s1[-1], s2[-1]) == oracle.width_sums(lat, H0)
+    b.free()
+
+
+@pytest.mark.parametrize("threads,wgs", [(256, 0), (512, 96), (1024, 7), (1024, 0)])
+def test_mapping_does_not_change_results(okpz, threads, wgs):
+    refs = [alone(okpz, j, M) for j in MIXED[:8]]
+    b = okpz.Batch(MIXED[:8], M)
+    b.set_mapping(threads, wgs)
+    b.run()
+    check_batch(okpz, b, MIXED[:8], M, refs)
+    b.free()
+
+
+def test_many_tiny_jobs(okpz):
+    jobs = [(32 * (1 + r % 4), 32, 1.0 if r % 2 else 0.9, 0.0 if r % 3 else 0.1, 100 + r,
+             5 + r % 17) for r in range(300)]
+    b = okpz.Batch(jobs, 0.5)
+    b.run()
+    for r in (0, 1, 2, 3, 17, 150, 299):
+        ref, lat, h0 = alone(okpz, jobs[r], 0.5)
+        t, s1, s2 = b.samples(r)
+        assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref
+        assert np.array_equal(b.get_lattice(r), lat) and b.h0(r) == h0
+    b.free()
+
+
+def test_autotune_then_run(okpz):
+    jobs = MIXED[:6]
+    refs = [alone(okpz, j, M) for j in jobs]
+    b = okpz.Batch(jobs, M)
+    threads, wgs = b.autotune(3)
+    assert threads in (256, 512, 1024) and wgs > 0
+    assert b.mapping() == (threads, wgs)
+    b.run()
+    check_batch(okpz, b, jobs, M, refs)
+    # a second run repeats the first exactly
+    b.run()
+    check_batch(okpz, b, jobs, M, refs)
+    b.free()
