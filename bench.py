@@ -23,7 +23,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-METRIC = "site updates/s (+% HBM roofline) at L=2^17; realizations/s batched vs plain"
+METRIC = "site updates/s (+% HBM roofline) at L=2^17; realizations/s batched vs plain; serving p50/p99"
+
+
+def log(msg):
+    """Progress of the legs on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def sampling_times(tmax, m=0.01):
@@ -58,6 +63,103 @@ def cpu_baseline(budget_s=12.0):
                       f"2^17 workload's 256x256 geometry), {el:.1f} s, OpenMP over blocks"}
 
 
+def ensemble_jobs(scale):
+    """The finite-size-scaling ensemble: 512 realizations, L = 32 (1 + r mod 32)
+    (32 sizes 32 .. 1024, 16 each), p = 1, q = 0, seed 1000 + r, run to
+    t = scale * 20 L^1.6 MCS (scale = 1 is the full steady-state run)."""
+    jobs = []
+    for r in range(512):
+        L = 32 * (1 + r % 32)
+        jobs.append((L, L, 1.0, 0.0, 1000 + r, max(1, int(math.ceil(scale * 20 * L ** 1.6)))))
+    return jobs
+
+
+def batch_leg(scale, m=0.001):
+    """Realizations/s of the ensemble: one persistent launch (after the
+    autotuner picks the mapping) vs a per-realization loop of okpz_sweep /
+    okpz_width launches, same jobs, same sampling times, same GPU."""
+    from paper_1110_6745_amd import okpz
+
+    jobs = ensemble_jobs(scale)
+    work = sum(L * L * t for L, _, _, _, _, t in jobs)
+    b = okpz.Batch(jobs, m)
+    t0 = time.perf_counter()
+    mapping = b.autotune(max(2, int(min(t for *_, t in jobs))))
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dev_ms = b.run()
+    batched_s = time.perf_counter() - t0
+    log(f"ensemble: batched {batched_s:.2f} s (mapping {mapping})")
+    # spot check: one job of each size class run alone gives the same samples
+    for r in (0, 31):
+        L, _, p, q, seed, t_max = jobs[r]
+        sim = okpz.okpz_init(L, L, p, q, seed)
+        ref = [(t,) + sim.width(t) for t in okpz.sampling_times(t_max, m)]
+        sim.free()
+        t, s1, s2 = b.samples(r)
+        assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref, "batched job differs"
+    hist_L = 1024
+    t_from = jobs[31][5] // 2
+    counts, under, over = b.w2_histogram(hist_L, hist_L, t_from, 0.0, 20.0, 40)
+    b.free()
+    t0 = time.perf_counter()
+    for L, _, p, q, seed, t_max in jobs:
+        sim = okpz.okpz_init(L, L, p, q, seed)
+        for t in okpz.sampling_times(t_max, m):
+            sim.width(t)
+        sim.free()
+    plain_s = time.perf_counter() - t0
+    return {"workload": f"512 realizations, L = 32..1024 step 32 (16 each), p=1 q=0, "
+                        f"t = {scale:g} x 20 L^1.6 MCS, W^2 at t_(i+1)=(t_i+10)e^{m:g}",
+            "site_updates": work, "batched_s": batched_s, "batched_device_ms": dev_ms,
+            "plain_s": plain_s, "realizations_per_s_batched": 512 / batched_s,
+            "realizations_per_s_plain": 512 / plain_s, "speedup": plain_s / batched_s,
+            "batched_site_updates_per_s": work / batched_s,
+            "mapping": {"threads": mapping[0], "workgroups": mapping[1], "autotune_s": tune_s},
+            "w2_histogram_L1024": {"t_from": t_from, "lo": 0.0, "hi": 20.0,
+                                   "counts": counts.tolist(), "under": under, "over": over}}
+
+
+def serve_leg(n_jobs=64, rate=50.0, seed=7, capacity=None):
+    """Continuous batching of a served job stream (Poisson arrivals, mean
+    1/rate s; L = 2^U{6..13}; p ~ U[0.6, 1]; q = 0 or 1 - p; t_max
+    log-uniform in [10^3, 10^4]; job seed = index + 1).  Runs the stream at
+    `rate` and, when `capacity` (site updates/s) is given, again at half of
+    that capacity; reports p50/p99 latency (finish - arrival), jobs/s and
+    achieved vs offered site updates/s."""
+    import numpy as np
+
+    from paper_1110_6745_amd import okpz
+
+    def one(r):
+        stream = okpz.job_stream(n_jobs, r, seed)
+        work = sum(L * L * t for _, (L, _, _, _, _, t) in stream)
+        sv = okpz.Server(hbm_budget=64 << 30, max_slots=64, quantum_sites=1 << 28, m=0.01)
+        t0 = sv.now() + 0.05
+        ids = [sv.submit(job, t0 + a) for a, job in stream]
+        sv.drain(timeout_s=300.0)
+        info = [sv.job(i) for i in ids]
+        st = sv.stats()
+        sv.free()
+        lat = np.array([j["finish"] - j["arrival"] for j in info])
+        span = max(j["finish"] for j in info) - t0
+        offered_span = stream[-1][0]
+        return {"jobs": n_jobs, "rate_jobs_per_s": r, "offered_site_updates_per_s": work / offered_span,
+                "achieved_site_updates_per_s": work / span, "jobs_per_s": n_jobs / span,
+                "latency_p50_s": float(np.percentile(lat, 50)),
+                "latency_p99_s": float(np.percentile(lat, 99)),
+                "quanta": st["quanta"], "device_s": st["device_ms"] / 1e3, "wall_s": span}
+
+    out = {"workload": f"{n_jobs} jobs, Poisson arrivals, L=2^U{{6..13}}, p~U[0.6,1], q=0 or 1-p, "
+                       f"t_max log-uniform [1e3,1e4], W^2 at t_(i+1)=(t_i+10)e^0.01, seed {seed}",
+           "at_rate": one(rate)}
+    if capacity:
+        stream = okpz.job_stream(n_jobs, 1.0, seed)
+        per_job = sum(L * L * t for _, (L, _, _, _, _, t) in stream) / n_jobs
+        out["at_half_capacity"] = one(0.5 * capacity / per_job)
+    return out
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -78,6 +180,9 @@ def main():
     ap.add_argument("--threads", type=int, default=1024, help="sweep workgroup size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib", action="store_true", help="run a 1 GiB copy first (counters)")
+    ap.add_argument("--batch-scale", type=float, default=0.005,
+                    help="ensemble leg: fraction of the full t = 20 L^1.6 (0 skips it)")
+    ap.add_argument("--serve-jobs", type=int, default=64, help="serving leg: jobs (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent "
@@ -151,8 +256,16 @@ def main():
     sim.free()
     del buf
     torch.cuda.synchronize()
+    log(f"sweep leg: {sweep_ms:.3f} ms per MCS, {value:.4g} site updates/s")
+    if args.batch_scale > 0:
+        out["batched_vs_plain"] = batch_leg(args.batch_scale)
+        log(f"ensemble leg: speedup {out['batched_vs_plain']['speedup']:.3g}")
+    if args.serve_jobs > 0:
+        out["serving"] = serve_leg(args.serve_jobs, 50.0, capacity=out["sweep_site_updates_per_s"])
+        log("serving leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

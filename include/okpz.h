@@ -166,6 +166,13 @@ int okpz_batch_last_ms(okpz_batch *b, float *ms);
 int okpz_batch_samples(okpz_batch *b, int32_t job, int64_t *t, int64_t *sum_h, int64_t *sum_h2,
                        int32_t cap, int32_t *count);
 
+/* Histogram of W^2 = sum_h2/N - (sum_h/N)^2 over the samples with t >= t_from
+ * of every job of size Lx x Ly: nbins equal bins on [lo, hi) into counts,
+ * samples below lo / at or above hi into *under / *over (may be NULL).
+ * The steady-state width distribution of Sec. IV comes from such samples. */
+int okpz_batch_w2_histogram(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, double lo,
+                            double hi, int32_t nbins, int64_t *counts, int64_t *under, int64_t *over);
+
 /* Final state of one job: canonical lattice (bytes >= Lx*Ly) and H0. */
 int okpz_batch_get_lattice(okpz_batch *b, int32_t job, uint8_t *host, size_t bytes);
 int okpz_batch_h0(okpz_batch *b, int32_t job, int64_t *h0);
@@ -174,6 +181,43 @@ int okpz_batch_free(okpz_batch *b);
 
 /* Message of the last batch error on this thread. */
 const char *okpz_batch_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of simulation jobs.  Jobs are submitted with
+ * an arrival time (seconds on the server's clock; < 0 = now).  Each
+ * okpz_serve_step is one quantum: arrived jobs are admitted in arrival order
+ * while a slot is free and their device bytes fit hbm_budget (their lattices
+ * then stay resident until they finish); one persistent launch advances every
+ * resident job by about quantum_sites site updates (at least one MCS), all
+ * jobs' work interleaved on the device; finished jobs are retired and their
+ * memory freed.  Results are bit for bit those of the job run alone.
+ * ---------------------------------------------------------------------- */
+typedef struct okpz_server okpz_server; /* opaque */
+
+int okpz_serve_create(okpz_server **out, size_t hbm_budget, int32_t max_slots,
+                      int64_t quantum_sites, double m);
+int okpz_serve_set_mapping(okpz_server *sv, int32_t threads, int32_t workgroups);
+/* Seconds since the server was created. */
+int okpz_serve_now(okpz_server *sv, double *now);
+/* Queue a job; OKPZ_EBUSY if it could never fit the budget.  keep_lattice:
+ * keep the final lattice on the host for okpz_serve_result. */
+int okpz_serve_submit(okpz_server *sv, const okpz_job *job, double arrival_s, int32_t keep_lattice,
+                      int64_t *id);
+/* One quantum (admission, one launch, retirement).  Returns at once with
+ * *running = 0 if nothing is resident. */
+int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting);
+/* Job status (0 waiting, 1 running, 2 done) and its clock times (-1 if not yet). */
+int okpz_serve_job(okpz_server *sv, int64_t id, int32_t *state, double *arrival, double *admit,
+                   double *finish);
+/* Samples of a finished job (as okpz_batch_samples). */
+int okpz_serve_samples(okpz_server *sv, int64_t id, int64_t *t, int64_t *sum_h, int64_t *sum_h2,
+                       int32_t cap, int32_t *count);
+/* Final H0 and, if kept, the canonical final lattice of a finished job. */
+int okpz_serve_result(okpz_server *sv, int64_t id, uint8_t *host, size_t bytes, int64_t *h0);
+/* Quanta run, device milliseconds, jobs done, device bytes held by jobs. */
+int okpz_serve_stats(okpz_server *sv, int64_t *quanta, double *device_ms, int64_t *done,
+                     size_t *bytes_in_use);
+int okpz_serve_free(okpz_server *sv);
 
 #ifdef __cplusplus
 }

@@ -2,20 +2,23 @@
 // each with its own p, q, seed and length, run to completion in ONE
 // persistent launch (ensembles of independent runs, Sec. III and IV).
 //
-// Work item = (job, group of blocks) of the job's current sweep.  Resident
-// workgroups take items from a bounded multi-producer multi-consumer ring in
-// device memory; the workgroup that completes the last group of a job's sweep
-// advances the job (time, stored offset, lattice copy), measures the exact
-// width when a sampling time is reached, and enqueues the job's next sweep.
-// No workgroup ever waits for a particular other workgroup, so the launch
-// needs no co-residency; a workgroup that finds the ring empty sleeps
-// briefly and retries, and a global progress counter acts as watchdog: if no
-// group completes anywhere for a long time every workgroup exits with an
-// error flag instead of spinning forever.
+// Work item = (job, group of blocks) of the job's current sweep.  Each job
+// has a claim word (sweep << 32 | next group); a resident workgroup's first
+// wavefront scans the claim words, 64 jobs per load, and claims a group of a
+// job with one fetch-and-add on that job's word, so contention is spread
+// over the jobs.  The workgroup that completes the last group of a job's
+// sweep advances the job (time, stored offset, lattice copy), measures the
+// exact width when a sampling time is reached, and reopens the job's claim
+// word for the next sweep.  No workgroup ever waits for a particular other
+// workgroup, so the launch needs no co-residency; a workgroup that finds no
+// open group sleeps briefly and rescans, and a global progress counter acts
+// as watchdog: if no group completes anywhere for a long time every
+// workgroup exits with an error flag instead of spinning forever.
 //
 // Memory ordering: lattice words written by one workgroup are read by the
-// next sweep's workgroups on any XCD; each group completion releases at agent
-// scope (writes back the XCD's L2) and every dequeue acquires at agent scope.
+// next sweep's workgroups on any XCD.  Scans are relaxed loads; a successful
+// claim is followed by one agent-scope acquire, a completed group by one
+// acquire-release count, and a reopened job by one release.
 //
 // A job's trajectory is identical to the same job run alone through
 // okpz_sweep: the random decisions are keyed by (seed, sweep, block, step,
@@ -60,72 +63,22 @@ struct JobState {
 };
 
 struct Control {
-    uint64_t head, tail;  // ring positions
-    uint64_t progress;    // groups completed by the whole launch
-    int32_t finished;     // jobs that reached t_max
-    int32_t error;        // 1: watchdog, 2: ring full
+    uint64_t progress;  // groups completed by the whole launch
+    int32_t finished;   // jobs that reached their stop target
+    int32_t error;      // 1: watchdog
 };
 
-__device__ __forceinline__ uint64_t ld_acq(uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
+// claim[r] = (sweep << 32) | next group to hand out; job r has an open group
+// while the low word is below ngroups[r].  A finished or empty job holds
+// kClosed in the low word.  A scan can see a word open that is exhausted or
+// closed by the time the wave's fetch-and-add lands; such late increments
+// are at most one per workgroup per word value, so the low word never
+// carries into the sweep number (kClosed + workgroups < 2^32).
+constexpr uint32_t kClosed = 0x80000000u;
+
 __device__ __forceinline__ uint64_t ld_rlx(uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ bool cas(uint64_t *p, uint64_t &expect, uint64_t want)
-{
-    return __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_ACQ_REL,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Bounded MPMC ring (sequence-numbered cells).  Returns false if full.
-__device__ bool enqueue(Control *c, uint64_t *seq, uint64_t *val, uint64_t mask, uint64_t item)
-{
-    uint64_t pos = ld_rlx(&c->tail);
-    for (int tries = 0; tries < (1 << 20); ++tries) {
-        const uint64_t sq = ld_acq(&seq[pos & mask]);
-        const int64_t dif = (int64_t)(sq - pos);
-        if (dif == 0) {
-            if (cas(&c->tail, pos, pos + 1)) {
-                __hip_atomic_store(&val[pos & mask], item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st_rel(&seq[pos & mask], pos + 1);
-                return true;
-            }
-        } else if (dif < 0) {
-            return false;
-        } else {
-            pos = ld_rlx(&c->tail);
-        }
-    }
-    return false;
-}
-
-// Returns true and the item, or false if the ring is empty.
-__device__ bool dequeue(Control *c, uint64_t *seq, uint64_t *val, uint64_t mask, uint64_t *item)
-{
-    uint64_t pos = ld_rlx(&c->head);
-    for (int tries = 0; tries < (1 << 20); ++tries) {
-        const uint64_t sq = ld_acq(&seq[pos & mask]);
-        const int64_t dif = (int64_t)(sq - (pos + 1));
-        if (dif == 0) {
-            if (cas(&c->head, pos, pos + 1)) {
-                *item = __hip_atomic_load(&val[pos & mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st_rel(&seq[pos & mask], pos + mask + 1);
-                return true;
-            }
-        } else if (dif < 0) {
-            return false;
-        } else {
-            pos = ld_rlx(&c->head);
-        }
-    }
-    return false;
 }
 
 __device__ inline SweepLaunch make_launch(const JobDesc &jd, const JobState &js)
@@ -168,70 +121,109 @@ __device__ __forceinline__ void run_group(const SweepLaunch &a, int b0, int G, u
         core::sweep_group<kThreads, kMode, 0>(a, b0, G, smem, opk);
 }
 
-// Publish job r's next sweep (or count it finished).  Thread 0 only.
-__device__ void advance(const JobDesc &jd, JobState *js, Control *ctl, uint64_t *qseq,
-                        uint64_t *qval, uint64_t qmask, int r)
+// Publish job r's next sweep (or count it finished).  Thread 0 only, after
+// the job's state for the new sweep has been written.
+__device__ void publish(const JobDesc &jd, const JobState &ns, Control *ctl, uint64_t *claim, int r)
 {
-    if (js->s >= jd.t_max) {
+    if (ns.s >= jd.t_max) {
+        __hip_atomic_store(&claim[r], ((uint64_t)ns.s << 32) | kClosed, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&ctl->finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    for (int g = 0; g < jd.ngroups; ++g) {
-        if (!enqueue(ctl, qseq, qval, qmask, ((uint64_t)r << 32) | (uint32_t)g)) {
-            __hip_atomic_store(&ctl->error, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
+    __atomic_thread_fence(__ATOMIC_RELEASE);  // state and lattice before the claim word
+    __hip_atomic_store(&claim[r], (uint64_t)ns.s << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0 looks for a job with an open group and claims one.  Returns the
+// job index and writes the claimed (sweep << 32 | group), or -1.
+__device__ int find_and_claim(uint64_t *claim, const int32_t *ngr, int njobs, int start,
+                              uint64_t *got)
+{
+    const int lane = threadIdx.x & 63;
+    for (int base = 0; base < njobs; base += 64) {
+        int r = start + base + lane;
+        if (r >= njobs) r -= njobs;
+        if (r >= njobs) r -= njobs;
+        bool open = false;
+        if (base + lane < njobs) {
+            const uint64_t w = ld_rlx(&claim[r]);
+            open = (uint32_t)w < (uint32_t)ngr[r];
+        }
+        uint64_t mask = __ballot(open);
+        while (mask) {
+            const int pick = __ffsll((unsigned long long)mask) - 1;
+            const int rr = __shfl(r, pick, 64);
+            uint64_t w = 0;
+            if (lane == 0)
+                w = __hip_atomic_fetch_add(&claim[rr], (uint64_t)1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            w = __shfl(w, 0, 64);
+            if ((uint32_t)w < (uint32_t)ngr[rr]) {
+                *got = w;
+                return rr;
+            }
+            mask &= mask - 1;  // that job ran out meanwhile; try the next one
         }
     }
+    return -1;
 }
 
 template <int kThreads>
 __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, JobState *state,
-                                                         Control *ctl, uint64_t *qseq, uint64_t *qval,
-                                                         uint64_t qmask, int32_t njobs,
+                                                         Control *ctl, uint64_t *claim,
+                                                         const int32_t *ngr, int32_t njobs,
                                                          uint64_t idle_limit)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint64_t s_item;
-    __shared__ int s_cmd;    // 0: work, 1: exit, 2: retry
-    __shared__ int s_width;  // 1: the job just reached a sampling time
+    __shared__ int s_job;     // >= 0: work; -1: exit; -2: retry
+    __shared__ uint64_t s_claim;
+    __shared__ int s_width;   // 1: the job just reached a sampling time
     __shared__ int64_t s_out[4];
     const int tid = threadIdx.x;
     uint64_t idle = 0, seen = 0;
+    int start = (int)((blockIdx.x * 61u) % (uint32_t)njobs);
 
     while (true) {
-        if (tid == 0) {
-            uint64_t item = 0;
-            int cmd = 2;
-            if (dequeue(ctl, qseq, qval, qmask, &item)) {
-                cmd = 0;
-                idle = 0;
-            } else if (__hip_atomic_load(&ctl->finished, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= njobs ||
-                       __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                cmd = 1;
-            } else {
-                const uint64_t p = ld_rlx(&ctl->progress);
-                if (p != seen) {
-                    seen = p;
+        if (tid < 64) {
+            uint64_t w = 0;
+            int r = find_and_claim(claim, ngr, njobs, start, &w);  // uniform over wave 0
+            if (r >= 0) start = r;  // every lane scans from the same place next time
+            if (tid == 0) {
+                if (r >= 0) {
+                    __atomic_thread_fence(__ATOMIC_ACQUIRE);  // the job's state and lattice
                     idle = 0;
-                } else if (++idle > idle_limit) {
-                    __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    cmd = 1;
+                } else if (__hip_atomic_load(&ctl->finished, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_AGENT) >= njobs ||
+                           __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    r = -1;
+                } else {
+                    const uint64_t p = ld_rlx(&ctl->progress);
+                    if (p != seen) {
+                        seen = p;
+                        idle = 0;
+                    } else if (++idle > idle_limit) {
+                        __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        r = -1;
+                    }
+                    if (r != -1) {
+                        r = -2;
+                        __builtin_amdgcn_s_sleep(16);
+                    }
                 }
-                __builtin_amdgcn_s_sleep(8);
+                s_job = r;
+                s_claim = w;
             }
-            s_item = item;
-            s_cmd = cmd;
         }
         __syncthreads();
-        const int cmd = s_cmd;
-        const uint64_t item = s_item;
+        const int r = s_job;
+        const uint64_t w = s_claim;
         __syncthreads();
-        if (cmd == 1) break;
-        if (cmd == 2) continue;
+        if (r == -1) break;
+        if (r == -2) continue;
 
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);  // every thread: see the job's state and lattice
-        const int r = (int)(item >> 32), gi = (int)(item & 0xffffffffu);
+        const int gi = (int)(uint32_t)w;
         const JobDesc jd = jobs[r];
         const JobState js = state[r];
         const SweepLaunch a = make_launch(jd, js);
@@ -247,8 +239,8 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
 
         if (tid == 0) {
             s_width = 0;
-            __atomic_thread_fence(__ATOMIC_RELEASE);
             __hip_atomic_fetch_add(&ctl->progress, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // release this group's lattice words; the last group acquires all
             const uint32_t d = __hip_atomic_fetch_add(&state[r].done, 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_AGENT) + 1u;
             if (d == (uint32_t)jd.ngroups) {  // last group of sweep s: advance the job
@@ -262,19 +254,19 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
                 if (sample)
                     s_width = 1;
                 else
-                    advance(jd, &state[r], ctl, qseq, qval, qmask, r);
+                    publish(jd, ns, ctl, claim, r);
             }
         }
         __syncthreads();
         if (s_width) {
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
             const JobState ns = state[r];
             const LatticeView v{ns.cur ? jd.buf[1] : jd.buf[0], jd.Lx, jd.Ly, jd.W, ns.ox};
             const int lane = tid & 63, wave = tid >> 6, nwave = kThreads / 64;
-            for (int y = wave; y < jd.Ly; y += nwave) core::width_row(v, y, lane, jd.rows);
-            __atomic_thread_fence(__ATOMIC_RELEASE);
+            uint32_t *lut = reinterpret_cast<uint32_t *>(smem + 20 * 1024);
+            core::width_lut_build(lut);
             __syncthreads();
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            for (int y = wave; y < jd.Ly; y += nwave) core::width_row(v, y, lane, lut, jd.rows);
+            __syncthreads();  // rows are read back by other waves of this workgroup (same CU)
             int32_t *scan = reinterpret_cast<int32_t *>(smem);
             int64_t *r1 = reinterpret_cast<int64_t *>(smem + 4 * 1024);
             int64_t *r2 = reinterpret_cast<int64_t *>(smem + 12 * 1024);
@@ -287,20 +279,34 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
                 o[3] = s_out[2];
                 o[4] = s_out[3];
                 o[5] = __hip_atomic_load(jd.h0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                state[r].next_sample = ns.next_sample + 1;
-                advance(jd, &state[r], ctl, qseq, qval, qmask, r);
+                JobState n2 = ns;
+                n2.next_sample = ns.next_sample + 1;
+                state[r] = n2;
+                publish(jd, n2, ctl, claim, r);
             }
             __syncthreads();
         }
     }
 }
 
+// Flat zig-zag state h = (x+y) mod 2 in copy 0 of every job, H0 = 0.
 __global__ void init_jobs_kernel(const JobDesc *jobs, int32_t njobs)
 {
-    // flat zig-zag state h = (x+y) mod 2 in copy 0 of every job, H0 = 0
     const int r = blockIdx.y;
     if (r >= njobs) return;
     const JobDesc jd = jobs[r];
+    const size_t n = 2 * (size_t)jd.Ly * jd.W;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t y = (e / jd.W) % jd.Ly;
+        jd.buf[0][e] = (y & 1) ? 0xAAAAAAAAu : 0x55555555u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *jd.h0 = 0;
+}
+
+// Flat state in copy 0 of one job, H0 = 0.
+__global__ void init_one_kernel(JobDesc jd)
+{
     const size_t n = 2 * (size_t)jd.Ly * jd.W;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
          e += (size_t)gridDim.x * blockDim.x) {
@@ -329,8 +335,8 @@ struct okpz_batch {
     JobDesc *d_desc = nullptr;
     JobState *d_state = nullptr;
     Control *d_ctl = nullptr;
-    uint64_t *d_qseq = nullptr, *d_qval = nullptr;
-    uint64_t qcap = 0;
+    uint64_t *d_claim = nullptr;
+    int32_t *d_ngr = nullptr;
     int threads = 1024;
     int workgroups = 0;  // 0: two per compute unit
     int cus = 0;
@@ -386,35 +392,29 @@ int reset(okpz_batch *b, const std::vector<int32_t> &tmax)
     std::vector<JobState> st(n);
     std::memset(st.data(), 0, st.size() * sizeof(JobState));
     std::vector<JobDesc> desc = b->desc;
-    uint64_t n0 = 0;
-    std::vector<uint64_t> qseq(b->qcap), qval(b->qcap, 0);
+    std::vector<uint64_t> claim(n);
+    std::vector<int32_t> ngr(n);
+    int finished = 0;
     for (int r = 0; r < n; ++r) {
         desc[r].t_max = tmax[r];
         // sampling times beyond the limit are not reached
         int ns = 0;
         while (ns < (int)b->times[r].size() && b->times[r][ns] <= tmax[r]) ++ns;
         desc[r].nsamp = ns;
-    }
-    int finished = 0;
-    for (int r = 0; r < n; ++r) {
+        ngr[r] = desc[r].ngroups;
         if (desc[r].t_max == 0) {
+            claim[r] = okpz::batch::kClosed;
             ++finished;
-            continue;
-        }
-        for (int g = 0; g < desc[r].ngroups; ++g) {
-            qval[n0] = ((uint64_t)r << 32) | (uint32_t)g;
-            ++n0;
+        } else {
+            claim[r] = 0;  // sweep 0, group 0
         }
     }
-    for (uint64_t i = 0; i < b->qcap; ++i) qseq[i] = (i < n0) ? i + 1 : i;
     Control ctl{};
-    ctl.head = 0;
-    ctl.tail = n0;
     ctl.finished = finished;
     BHIP(hipMemcpyAsync(b->d_desc, desc.data(), n * sizeof(JobDesc), hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_state, st.data(), n * sizeof(JobState), hipMemcpyHostToDevice, b->stream));
-    BHIP(hipMemcpyAsync(b->d_qseq, qseq.data(), b->qcap * 8, hipMemcpyHostToDevice, b->stream));
-    BHIP(hipMemcpyAsync(b->d_qval, qval.data(), b->qcap * 8, hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(b->d_claim, claim.data(), n * 8, hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(b->d_ngr, ngr.data(), n * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, b->stream));
     int maxwords = 0;
     for (auto &d : desc) maxwords = std::max(maxwords, 2 * d.Ly * d.W);
@@ -425,8 +425,19 @@ int reset(okpz_batch *b, const std::vector<int32_t> &tmax)
     return OKPZ_OK;
 }
 
+// Device pointers of one persistent launch over a job table.
+struct Ring {
+    JobDesc *desc;
+    JobState *state;
+    Control *ctl;
+    uint64_t *claim;
+    int32_t *ngr;
+    int njobs;
+    hipStream_t stream;
+};
+
 template <int kThreads>
-hipError_t launch_batch(okpz_batch *b, int wgs)
+hipError_t launch_ring(const Ring &R, int wgs)
 {
     static bool attr = false;
     if (!attr) {
@@ -436,13 +447,40 @@ hipError_t launch_batch(okpz_batch *b, int wgs)
         if (e != hipSuccess) return e;
         attr = true;
     }
-    // about 2 s without any group completing anywhere (one probe: a dequeue
-    // attempt plus a sleep of 8 x 64 cycles)
-    const uint64_t idle_limit = 1ull << 20;
+    // about 2 s without any group completing anywhere (one probe: a scan of
+    // the claim words plus a sleep of 16 x 64 cycles)
+    const uint64_t idle_limit = 1ull << 19;
     hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads>), dim3(wgs), dim3(kThreads),
-                       okpz::core::kGroupLds, b->stream, b->d_desc, b->d_state, b->d_ctl, b->d_qseq,
-                       b->d_qval, b->qcap - 1, (int32_t)b->jobs.size(), idle_limit);
+                       okpz::core::kGroupLds, R.stream, R.desc, R.state, R.ctl, R.claim, R.ngr,
+                       (int32_t)R.njobs, idle_limit);
     return hipGetLastError();
+}
+
+hipError_t launch_any(const Ring &R, int threads, int wgs)
+{
+    switch (threads) {
+    case 256: return launch_ring<256>(R, wgs);
+    case 512: return launch_ring<512>(R, wgs);
+    default: return launch_ring<1024>(R, wgs);
+    }
+}
+
+// After a launch: OKPZ_OK if every job reached its stop target.
+int check_control(const Ring &R)
+{
+    Control ctl;
+    BHIP(hipMemcpy(&ctl, R.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    if (ctl.error == 1)
+        return bfail(OKPZ_EDEVICE, "persistent launch watchdog: no progress (finished %d of %d)",
+                     ctl.finished, R.njobs);
+    if (ctl.finished != R.njobs)
+        return bfail(OKPZ_EDEVICE, "launch ended with %d of %d jobs finished", ctl.finished, R.njobs);
+    return OKPZ_OK;
+}
+
+Ring ring_of(okpz_batch *b)
+{
+    return Ring{b->d_desc, b->d_state, b->d_ctl, b->d_claim, b->d_ngr, (int)b->jobs.size(), b->stream};
 }
 
 int run(okpz_batch *b, int threads, int wgs, float *ms)
@@ -451,12 +489,8 @@ int run(okpz_batch *b, int threads, int wgs, float *ms)
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     BHIP(hipEventRecord(e0, b->stream));
-    hipError_t e;
-    switch (threads) {
-    case 256: e = launch_batch<256>(b, wgs); break;
-    case 512: e = launch_batch<512>(b, wgs); break;
-    default: e = launch_batch<1024>(b, wgs); break;
-    }
+    const Ring R = ring_of(b);
+    hipError_t e = launch_any(R, threads, wgs);
     if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "batch launch: %s", hipGetErrorString(e));
     BHIP(hipEventRecord(e1, b->stream));
     BHIP(hipStreamSynchronize(b->stream));
@@ -465,15 +499,7 @@ int run(okpz_batch *b, int threads, int wgs, float *ms)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (ms) *ms = t;
-    Control ctl;
-    BHIP(hipMemcpy(&ctl, b->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
-    if (ctl.error == 1) return bfail(OKPZ_EDEVICE, "batch watchdog: no progress (finished %d of %zu)",
-                                     ctl.finished, b->jobs.size());
-    if (ctl.error == 2) return bfail(OKPZ_EDEVICE, "batch work ring overflow");
-    if (ctl.finished != (int)b->jobs.size())
-        return bfail(OKPZ_EDEVICE, "batch ended with %d of %zu jobs finished", ctl.finished,
-                     b->jobs.size());
-    return OKPZ_OK;
+    return check_control(R);
 }
 
 }  // namespace
@@ -538,10 +564,9 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
         total += 2 * lat + al(8) + al(3 * (size_t)j.Ly * 8) + al(6 * 8 * (size_t)std::max(1, d.nsamp)) +
                  al(4 * (size_t)std::max(1, d.nsamp));
     }
-    b->qcap = 1;
-    while (b->qcap < groups + 1) b->qcap <<= 1;
+    (void)groups;
     const size_t qoff = total;
-    total += 2 * al(b->qcap * 8);
+    total += al((size_t)n_jobs * 8) + al((size_t)n_jobs * 4);
     hipError_t e = hipMalloc(&b->mem, total);
     if (e != hipSuccess) {
         delete b;
@@ -552,8 +577,8 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
     b->d_state = reinterpret_cast<JobState *>(base + al(n_jobs * sizeof(JobDesc)));
     b->d_ctl = reinterpret_cast<Control *>(base + al(n_jobs * sizeof(JobDesc)) +
                                            al(n_jobs * sizeof(JobState)));
-    b->d_qseq = reinterpret_cast<uint64_t *>(base + qoff);
-    b->d_qval = reinterpret_cast<uint64_t *>(base + qoff + al(b->qcap * 8));
+    b->d_claim = reinterpret_cast<uint64_t *>(base + qoff);
+    b->d_ngr = reinterpret_cast<int32_t *>(base + qoff + al((size_t)n_jobs * 8));
     for (int r = 0; r < n_jobs; ++r) {
         const okpz_job &j = jobs[r];
         JobDesc &d = b->desc[r];
@@ -692,6 +717,38 @@ int okpz_batch_samples(okpz_batch *b, int32_t job, int64_t *t, int64_t *sum_h, i
     return OKPZ_OK;
 }
 
+int okpz_batch_w2_histogram(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, double lo,
+                            double hi, int32_t nbins, int64_t *counts, int64_t *under, int64_t *over)
+{
+    if (!b || !counts) return bfail(OKPZ_EINVAL, "null argument");
+    if (nbins <= 0 || !(hi > lo)) return bfail(OKPZ_EINVAL, "need nbins > 0 and hi > lo");
+    for (int i = 0; i < nbins; ++i) counts[i] = 0;
+    int64_t u = 0, o = 0;
+    for (int32_t r = 0; r < (int32_t)b->jobs.size(); ++r) {
+        if (b->jobs[r].Lx != Lx || b->jobs[r].Ly != Ly) continue;
+        int32_t n = 0;
+        int rc = okpz_batch_samples(b, r, nullptr, nullptr, nullptr, 0, &n);
+        if (rc != OKPZ_OK) return rc;
+        std::vector<int64_t> t(n), s1(n), s2(n);
+        rc = okpz_batch_samples(b, r, t.data(), s1.data(), s2.data(), n, &n);
+        if (rc != OKPZ_OK) return rc;
+        const __int128 N = (__int128)Lx * Ly;
+        for (int i = 0; i < n; ++i) {
+            if (t[i] < t_from) continue;
+            // W^2 = (N S2 - S1^2) / N^2 from the exact integer numerator
+            const __int128 num = N * (__int128)s2[i] - (__int128)s1[i] * s1[i];
+            const double w2 = (double)num / ((double)N * (double)N);
+            const double f = (w2 - lo) / (hi - lo) * nbins;
+            if (f < 0) ++u;
+            else if (f >= nbins) ++o;
+            else ++counts[(int)f];
+        }
+    }
+    if (under) *under = u;
+    if (over) *over = o;
+    return OKPZ_OK;
+}
+
 int okpz_batch_h0(okpz_batch *b, int32_t job, int64_t *h0)
 {
     if (!b || !h0) return bfail(OKPZ_EINVAL, "null argument");
@@ -731,5 +788,440 @@ int okpz_batch_free(okpz_batch *b)
 }
 
 const char *okpz_batch_last_error(void) { return b_err.c_str(); }
+
+}  // extern "C"
+
+
+// ===========================================================================
+// Serving: continuous batching of simulation jobs
+// ===========================================================================
+//
+// Jobs are submitted with an arrival time.  Each call to okpz_serve_step is
+// one quantum: jobs whose arrival time has passed are admitted in arrival
+// order while a slot is free and their device bytes fit the HBM budget (their
+// lattices are allocated and stay resident until they finish); then one
+// persistent launch advances every resident job by its quantum share of
+// sweeps, all jobs' groups interleaved on the device; finished jobs are
+// retired (samples copied out, memory freed) and their latency recorded.  A
+// job's share is about quantum_sites site updates (at least one sweep;
+// lattices below 512 x 512 are counted as 512 x 512 so that a small job's
+// sequential sweeps do not stretch the quantum).  A job's results do not
+// depend on when it ran or with which other jobs.
+#include <chrono>
+#include <deque>
+
+namespace {
+
+struct ServeJob {
+    okpz_job job{};
+    double arrival = 0, admit = -1, finish = -1;
+    int state = 0;  // 0 waiting, 1 running, 2 done
+    int slot = -1;
+    bool keep_lattice = false;
+    size_t bytes = 0;
+    void *mem = nullptr;
+    JobDesc desc{};
+    std::vector<int32_t> times;
+    int32_t s = 0;  // MCS completed (host mirror)
+    std::vector<int64_t> raw;
+    std::vector<uint8_t> lattice;
+    int64_t h0 = 0;
+};
+
+size_t job_bytes(const okpz_job &j, size_t nsamp)
+{
+    const size_t lat = al(2 * (size_t)j.Ly * (size_t)(j.Lx / 32) * 4);
+    return 2 * lat + al(8) + al(3 * (size_t)j.Ly * 8) + al(6 * 8 * std::max<size_t>(1, nsamp)) +
+           al(4 * std::max<size_t>(1, nsamp));
+}
+
+}  // namespace
+
+struct okpz_server {
+    size_t budget = 0, used = 0;
+    int max_slots = 0;
+    int64_t quantum_sites = 0;
+    double m = 0.01;
+    std::vector<ServeJob> jobs;
+    std::deque<int64_t> waiting;  // sorted by arrival
+    std::vector<int64_t> slot_job;
+    void *mem = nullptr;
+    JobDesc *d_desc = nullptr;
+    JobState *d_state = nullptr;
+    Control *d_ctl = nullptr;
+    uint64_t *d_claim = nullptr;
+    int32_t *d_ngr = nullptr;
+    hipStream_t stream = nullptr;
+    int threads = 1024, wgs = 0, cus = 0;
+    std::chrono::steady_clock::time_point t0;
+    int64_t quanta = 0, done = 0;
+    double device_ms = 0;
+};
+
+namespace {
+
+double now_s(const okpz_server *s)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+int retire(okpz_server *sv, ServeJob &J, double t)
+{
+    const JobDesc &d = J.desc;
+    J.raw.assign(6 * (size_t)d.nsamp, 0);
+    if (d.nsamp)
+        BHIP(hipMemcpy(J.raw.data(), d.samples, 6 * 8 * (size_t)d.nsamp, hipMemcpyDeviceToHost));
+    BHIP(hipMemcpy(&J.h0, d.h0, 8, hipMemcpyDeviceToHost));
+    if (J.keep_lattice) {
+        JobState st;
+        BHIP(hipMemcpy(&st, sv->d_state + J.slot, sizeof st, hipMemcpyDeviceToHost));
+        std::vector<uint32_t> pl(2 * (size_t)d.Ly * d.W);
+        BHIP(hipMemcpy(pl.data(), st.cur ? d.buf[1] : d.buf[0], pl.size() * 4, hipMemcpyDeviceToHost));
+        J.lattice.resize((size_t)d.Lx * d.Ly);
+        for (int64_t y = 0; y < d.Ly; ++y)
+            for (int64_t x = 0; x < d.Lx; ++x) {
+                const int64_t c = ((x - st.ox) % d.Lx + d.Lx) % d.Lx;
+                const uint32_t bx = (pl[(size_t)y * d.W + (c >> 5)] >> (c & 31)) & 1u;
+                const uint32_t by = (pl[((size_t)d.Ly + y) * d.W + (c >> 5)] >> (c & 31)) & 1u;
+                J.lattice[y * d.Lx + x] = (uint8_t)(bx | (by << 1));
+            }
+    }
+    BHIP(hipFree(J.mem));
+    J.mem = nullptr;
+    sv->used -= J.bytes;
+    sv->slot_job[J.slot] = -1;
+    J.slot = -1;
+    J.state = 2;
+    J.finish = t;
+    ++sv->done;
+    return OKPZ_OK;
+}
+
+int admit(okpz_server *sv, ServeJob &J, int slot, double t)
+{
+    const okpz_job &j = J.job;
+    J.bytes = job_bytes(j, J.times.size());
+    hipError_t e = hipMalloc(&J.mem, J.bytes);
+    if (e != hipSuccess) return bfail(OKPZ_ENOMEM, "hipMalloc(%zu): %s", J.bytes, hipGetErrorString(e));
+    okpz::Geometry g;
+    okpz::geometry_of(j.Lx, j.Ly, &g);
+    JobDesc &d = J.desc;
+    std::memset(&d, 0, sizeof d);
+    d.Lx = (int32_t)j.Lx;
+    d.Ly = (int32_t)j.Ly;
+    d.W = (int32_t)(j.Lx / 32);
+    d.Bx = g.Bx;
+    d.By = g.By;
+    d.nbx = (int32_t)(j.Lx / g.Bx);
+    d.nby = (int32_t)(j.Ly / g.By);
+    d.G = okpz::core::group_size(g.Bx, g.By, d.nbx * d.nby);
+    d.ngroups = (d.nbx * d.nby + d.G - 1) / d.G;
+    d.k0 = (uint32_t)(j.seed & 0xffffffffu);
+    d.k1 = (uint32_t)(j.seed >> 32);
+    d.Tp = okpz::threshold_of(j.p);
+    d.Tq = okpz::threshold_of(j.q);
+    const uint64_t one = uint64_t(1) << 32;
+    const bool trivial = (d.Tp == 0 || d.Tp == one) && (d.Tq == 0 || d.Tq == one);
+    d.mode = !trivial ? okpz::core::kDraw
+                      : (d.Tp == one && d.Tq == 0 ? okpz::core::kGrowth : okpz::core::kFixed);
+    d.t_max = (int32_t)j.t_max;
+    d.nsamp = (int32_t)J.times.size();
+    char *p = static_cast<char *>(J.mem);
+    const size_t lat = al(2 * (size_t)j.Ly * (size_t)(j.Lx / 32) * 4);
+    d.buf[0] = reinterpret_cast<uint32_t *>(p);
+    d.buf[1] = reinterpret_cast<uint32_t *>(p + lat);
+    d.h0 = reinterpret_cast<int64_t *>(p + 2 * lat);
+    d.rows = reinterpret_cast<int64_t *>(p + 2 * lat + al(8));
+    d.samples = reinterpret_cast<int64_t *>(p + 2 * lat + al(8) + al(3 * (size_t)j.Ly * 8));
+    int32_t *tt = reinterpret_cast<int32_t *>(p + 2 * lat + al(8) + al(3 * (size_t)j.Ly * 8) +
+                                               al(6 * 8 * std::max<size_t>(1, d.nsamp)));
+    d.sample_t = tt;
+    if (d.nsamp) BHIP(hipMemcpy(tt, J.times.data(), 4 * (size_t)d.nsamp, hipMemcpyHostToDevice));
+    const int bx = (int)std::min<size_t>(4096, (2 * (size_t)d.Ly * d.W + 255) / 256);
+    hipLaunchKernelGGL(okpz::batch::init_one_kernel, dim3(bx), dim3(256), 0, sv->stream, d);
+    BHIP(hipGetLastError());
+    JobState st;
+    std::memset(&st, 0, sizeof st);
+    BHIP(hipMemcpyAsync(sv->d_state + slot, &st, sizeof st, hipMemcpyHostToDevice, sv->stream));
+    BHIP(hipStreamSynchronize(sv->stream));
+    sv->used += J.bytes;
+    sv->slot_job[slot] = (int64_t)(&J - sv->jobs.data());
+    J.slot = slot;
+    J.state = 1;
+    J.admit = t;
+    J.s = 0;
+    return OKPZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int okpz_serve_create(okpz_server **out, size_t hbm_budget, int32_t max_slots,
+                      int64_t quantum_sites, double m)
+{
+    if (!out) return bfail(OKPZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots <= 0 || max_slots > 4096) return bfail(OKPZ_EINVAL, "max_slots must be in [1, 4096]");
+    if (quantum_sites <= 0) return bfail(OKPZ_EINVAL, "quantum_sites must be positive");
+    if (!(m > 0.0) || m > 10.0) return bfail(OKPZ_EINVAL, "sampling exponent m must be in (0, 10]");
+    if (hbm_budget == 0) return bfail(OKPZ_EINVAL, "hbm_budget must be positive");
+    okpz_server *sv = new okpz_server();
+    sv->budget = hbm_budget;
+    sv->max_slots = max_slots;
+    sv->quantum_sites = quantum_sites;
+    sv->m = m;
+    sv->slot_job.assign(max_slots, -1);
+    const size_t total = al(max_slots * sizeof(JobDesc)) + al(max_slots * sizeof(JobState)) +
+                         al(sizeof(Control)) + al((size_t)max_slots * 8) + al((size_t)max_slots * 4);
+    hipError_t e = hipMalloc(&sv->mem, total);
+    if (e != hipSuccess) {
+        delete sv;
+        return bfail(OKPZ_ENOMEM, "hipMalloc(%zu): %s", total, hipGetErrorString(e));
+    }
+    char *base = static_cast<char *>(sv->mem);
+    sv->d_desc = reinterpret_cast<JobDesc *>(base);
+    base += al(max_slots * sizeof(JobDesc));
+    sv->d_state = reinterpret_cast<JobState *>(base);
+    base += al(max_slots * sizeof(JobState));
+    sv->d_ctl = reinterpret_cast<Control *>(base);
+    base += al(sizeof(Control));
+    sv->d_claim = reinterpret_cast<uint64_t *>(base);
+    sv->d_ngr = reinterpret_cast<int32_t *>(base + al((size_t)max_slots * 8));
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (sv->cus <= 0) sv->cus = 256;
+    e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(sv->mem);
+        delete sv;
+        return bfail(OKPZ_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    sv->t0 = std::chrono::steady_clock::now();
+    *out = sv;
+    return OKPZ_OK;
+}
+
+int okpz_serve_set_mapping(okpz_server *sv, int32_t threads, int32_t workgroups)
+{
+    if (!sv) return bfail(OKPZ_EINVAL, "null server");
+    if (threads != 256 && threads != 512 && threads != 1024)
+        return bfail(OKPZ_EINVAL, "threads per workgroup must be 256, 512 or 1024");
+    if (workgroups < 0 || workgroups > (1 << 16)) return bfail(OKPZ_EINVAL, "workgroups out of range");
+    sv->threads = threads;
+    sv->wgs = workgroups;
+    return OKPZ_OK;
+}
+
+int okpz_serve_now(okpz_server *sv, double *now)
+{
+    if (!sv || !now) return bfail(OKPZ_EINVAL, "null argument");
+    *now = now_s(sv);
+    return OKPZ_OK;
+}
+
+int okpz_serve_submit(okpz_server *sv, const okpz_job *job, double arrival_s, int32_t keep_lattice,
+                      int64_t *id)
+{
+    if (!sv || !job || !id) return bfail(OKPZ_EINVAL, "null argument");
+    const okpz_job &j = *job;
+    if (!side_ok(j.Lx) || !side_ok(j.Ly))
+        return bfail(OKPZ_EINVAL, "sides must be multiples of 32 in [32, 8192]");
+    if (!(j.p >= 0.0 && j.p <= 1.0) || !(j.q >= 0.0 && j.q <= 1.0))
+        return bfail(OKPZ_EINVAL, "p and q must lie in [0,1]");
+    if (j.t_max < 0 || j.t_max >= (int64_t(1) << 31)) return bfail(OKPZ_EINVAL, "t_max out of range");
+    ServeJob J;
+    J.job = j;
+    J.arrival = arrival_s < 0 ? now_s(sv) : arrival_s;
+    J.keep_lattice = keep_lattice != 0;
+    J.times = sample_times(j.t_max, sv->m);
+    if (job_bytes(j, J.times.size()) > sv->budget)
+        return bfail(OKPZ_EBUSY, "job needs %zu bytes, more than the whole budget",
+                     job_bytes(j, J.times.size()));
+    sv->jobs.push_back(std::move(J));
+    const int64_t k = (int64_t)sv->jobs.size() - 1;
+    // keep the waiting list in arrival order (stable)
+    auto it = sv->waiting.end();
+    while (it != sv->waiting.begin() && sv->jobs[*(it - 1)].arrival > sv->jobs[k].arrival) --it;
+    sv->waiting.insert(it, k);
+    *id = k;
+    return OKPZ_OK;
+}
+
+int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
+{
+    if (!sv) return bfail(OKPZ_EINVAL, "null server");
+    double t = now_s(sv);
+    // 1. admission: arrival order, a free slot and the bytes must fit
+    while (!sv->waiting.empty()) {
+        ServeJob &J = sv->jobs[sv->waiting.front()];
+        if (J.arrival > t) break;
+        int slot = -1;
+        for (int i = 0; i < sv->max_slots; ++i)
+            if (sv->slot_job[i] < 0) {
+                slot = i;
+                break;
+            }
+        if (slot < 0 || sv->used + job_bytes(J.job, J.times.size()) > sv->budget) break;
+        int rc = admit(sv, J, slot, t);
+        if (rc != OKPZ_OK) return rc;
+        sv->waiting.pop_front();
+        if (J.job.t_max == 0) {
+            rc = retire(sv, J, now_s(sv));
+            if (rc != OKPZ_OK) return rc;
+        }
+    }
+    // 2. quantum: every resident job advances by its share
+    std::vector<JobDesc> desc(sv->max_slots);
+    std::vector<uint64_t> claim(sv->max_slots, okpz::batch::kClosed);
+    std::vector<int32_t> ngr(sv->max_slots, 0);
+    int active = 0, finished = 0;
+    for (int i = 0; i < sv->max_slots; ++i) {
+        std::memset(&desc[i], 0, sizeof(JobDesc));
+        const int64_t k = sv->slot_job[i];
+        if (k < 0) {
+            ++finished;
+            continue;
+        }
+        ServeJob &J = sv->jobs[k];
+        const int64_t L2 = std::max<int64_t>(J.job.Lx * J.job.Ly, 512 * 512);
+        const int64_t share = std::max<int64_t>(1, sv->quantum_sites / L2);
+        const int64_t stop = std::min<int64_t>(J.job.t_max, J.s + share);
+        desc[i] = J.desc;
+        desc[i].t_max = (int32_t)stop;
+        claim[i] = (uint64_t)J.s << 32;
+        ngr[i] = J.desc.ngroups;
+        ++active;
+    }
+    if (running) *running = active;
+    if (waiting) *waiting = (int32_t)sv->waiting.size();
+    if (active == 0) return OKPZ_OK;
+    Control ctl{};
+    ctl.finished = finished;
+    BHIP(hipMemcpyAsync(sv->d_desc, desc.data(), desc.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
+                        sv->stream));
+    BHIP(hipMemcpyAsync(sv->d_claim, claim.data(), claim.size() * 8, hipMemcpyHostToDevice, sv->stream));
+    BHIP(hipMemcpyAsync(sv->d_ngr, ngr.data(), ngr.size() * 4, hipMemcpyHostToDevice, sv->stream));
+    BHIP(hipMemcpyAsync(sv->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, sv->stream));
+    hipEvent_t e0, e1;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    BHIP(hipEventRecord(e0, sv->stream));
+    const Ring R{sv->d_desc, sv->d_state, sv->d_ctl, sv->d_claim, sv->d_ngr, sv->max_slots,
+                 sv->stream};
+    hipError_t e = launch_any(R, sv->threads, sv->wgs ? sv->wgs : 2 * sv->cus);
+    if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "serve launch: %s", hipGetErrorString(e));
+    BHIP(hipEventRecord(e1, sv->stream));
+    BHIP(hipStreamSynchronize(sv->stream));
+    float ms = 0.f;
+    BHIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    sv->device_ms += ms;
+    ++sv->quanta;
+    int rc = check_control(R);
+    if (rc != OKPZ_OK) return rc;
+    // 3. retire finished jobs
+    std::vector<JobState> st(sv->max_slots);
+    BHIP(hipMemcpy(st.data(), sv->d_state, st.size() * sizeof(JobState), hipMemcpyDeviceToHost));
+    t = now_s(sv);
+    for (int i = 0; i < sv->max_slots; ++i) {
+        const int64_t k = sv->slot_job[i];
+        if (k < 0) continue;
+        ServeJob &J = sv->jobs[k];
+        J.s = st[i].s;
+        if (J.s >= J.job.t_max) {
+            rc = retire(sv, J, t);
+            if (rc != OKPZ_OK) return rc;
+        }
+    }
+    if (running) {
+        int n = 0;
+        for (int i = 0; i < sv->max_slots; ++i) n += sv->slot_job[i] >= 0;
+        *running = n;
+    }
+    return OKPZ_OK;
+}
+
+int okpz_serve_job(okpz_server *sv, int64_t id, int32_t *state, double *arrival, double *admit_t,
+                   double *finish)
+{
+    if (!sv) return bfail(OKPZ_EINVAL, "null server");
+    if (id < 0 || id >= (int64_t)sv->jobs.size()) return bfail(OKPZ_EINVAL, "unknown job");
+    const ServeJob &J = sv->jobs[id];
+    if (state) *state = J.state;
+    if (arrival) *arrival = J.arrival;
+    if (admit_t) *admit_t = J.admit;
+    if (finish) *finish = J.finish;
+    return OKPZ_OK;
+}
+
+int okpz_serve_samples(okpz_server *sv, int64_t id, int64_t *t, int64_t *sum_h, int64_t *sum_h2,
+                       int32_t cap, int32_t *count)
+{
+    if (!sv || !count) return bfail(OKPZ_EINVAL, "null argument");
+    if (id < 0 || id >= (int64_t)sv->jobs.size()) return bfail(OKPZ_EINVAL, "unknown job");
+    const ServeJob &J = sv->jobs[id];
+    if (J.state != 2) return bfail(OKPZ_EINVAL, "job %lld has not finished", (long long)id);
+    const int n = (int)J.times.size();
+    *count = n;
+    if (!t && !sum_h && !sum_h2) return OKPZ_OK;
+    if (cap < n) return bfail(OKPZ_EINVAL, "capacity %d < %d samples", cap, n);
+    const __int128 N = (__int128)J.job.Lx * J.job.Ly;
+    const __int128 lim = (__int128)1 << 63;
+    for (int i = 0; i < n; ++i) {
+        const int64_t *o = &J.raw[6 * (size_t)i];
+        const __int128 s1r = (__int128)(((unsigned __int128)(uint64_t)o[2] << 64) | (uint64_t)o[1]);
+        const __int128 s2r = (__int128)(((unsigned __int128)(uint64_t)o[4] << 64) | (uint64_t)o[3]);
+        const __int128 H0 = o[5];
+        const __int128 S1 = s1r + N * H0;
+        const __int128 S2 = s2r + 2 * H0 * s1r + N * H0 * H0;
+        if (S1 >= lim || S1 < -lim || S2 >= lim || S2 < 0)
+            return bfail(OKPZ_EOVERFLOW, "job %lld sample %d exceeds int64", (long long)id, i);
+        if (t) t[i] = o[0];
+        if (sum_h) sum_h[i] = (int64_t)S1;
+        if (sum_h2) sum_h2[i] = (int64_t)S2;
+    }
+    return OKPZ_OK;
+}
+
+int okpz_serve_result(okpz_server *sv, int64_t id, uint8_t *host, size_t bytes, int64_t *h0)
+{
+    if (!sv) return bfail(OKPZ_EINVAL, "null server");
+    if (id < 0 || id >= (int64_t)sv->jobs.size()) return bfail(OKPZ_EINVAL, "unknown job");
+    const ServeJob &J = sv->jobs[id];
+    if (J.state != 2) return bfail(OKPZ_EINVAL, "job %lld has not finished", (long long)id);
+    if (h0) *h0 = J.h0;
+    if (host) {
+        if (!J.keep_lattice) return bfail(OKPZ_EINVAL, "job %lld did not keep its lattice", (long long)id);
+        if (bytes < J.lattice.size()) return bfail(OKPZ_EINVAL, "host buffer too small");
+        std::memcpy(host, J.lattice.data(), J.lattice.size());
+    }
+    return OKPZ_OK;
+}
+
+int okpz_serve_stats(okpz_server *sv, int64_t *quanta, double *device_ms, int64_t *done,
+                     size_t *bytes_in_use)
+{
+    if (!sv) return bfail(OKPZ_EINVAL, "null server");
+    if (quanta) *quanta = sv->quanta;
+    if (device_ms) *device_ms = sv->device_ms;
+    if (done) *done = sv->done;
+    if (bytes_in_use) *bytes_in_use = sv->used;
+    return OKPZ_OK;
+}
+
+int okpz_serve_free(okpz_server *sv)
+{
+    if (!sv) return OKPZ_OK;
+    if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    for (auto &J : sv->jobs)
+        if (J.mem) (void)hipFree(J.mem);
+    if (sv->mem) (void)hipFree(sv->mem);
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    delete sv;
+    return OKPZ_OK;
+}
 
 }  // extern "C"

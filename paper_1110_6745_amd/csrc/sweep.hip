@@ -43,7 +43,7 @@ hipError_t launch_b(const SweepLaunch &a, hipStream_t st)
     const int G = kFixedB ? 1 : core::group_size(a.Bx, a.By, nblk);
     const int ngroups = (nblk + G - 1) / G;
     const size_t lds = kFixedB ? 0
-                               : (size_t)(((G * (a.By + 1) * a.Bx) + 15) & ~15) + (size_t)G * 32 * 4;
+                               : (size_t)(((G * (a.By + 1) * a.Bx) + 15) & ~15) + (size_t)G * 35 * 4;
     static bool attr_set = false;
     if (!attr_set && !kFixedB) {
         // groups of up to ~74 KiB exceed the 64 KiB default of dynamic LDS

@@ -16,13 +16,16 @@
 //      this sweep's shift.  No two workgroups write the same word, so the
 //      store needs no atomics and the shift keeps one-site granularity.
 //
-// LDS byte of a site: bit 0 = bx (sigma_x = +1), bit 1 = by, bit 2 = block
-// border (dead) marker, bit 3 = copy of bx, bit 4 = copy of by.  For the site
-// s, its left neighbour l and lower neighbour d, the five-bit code
+// LDS byte of a site holds the complemented slope bits: bit 0 = nx
+// (sigma_x = -1), bit 1 = ny (sigma_y = -1), bit 2 = block border (dead)
+// marker, bit 3 = copy of nx, bit 4 = copy of ny.  For the site s, its left
+// neighbour l and lower neighbour d, the five-bit code
 //   k = (s & 7) | (l & 8) | (d & 16)
-// holds bx(u,v), by(u,v), dead(u,v), bx(u-1,v), by(u,v-1).  k = 3 is a local
-// minimum (-1 +1; -1 +1), k = 24 a local maximum; a dead site never matches.
-// An accepted move rewrites the three bytes (s ^ 0x1B, l ^ 0x09, d ^ 0x12).
+// holds nx(u,v), ny(u,v), dead(u,v), nx(u-1,v), ny(u,v-1).  k = 24 is a local
+// minimum (-1 +1; -1 +1), k = 3 a local maximum; a dead site never matches.
+// A minimum is thus s = 0 with l & 8 and d & 16 set, a test of two bit
+// operations.  An accepted move rewrites the three bytes (s ^ 0x1B, l ^ 0x09,
+// d ^ 0x12).
 // Within a step no other lane reads or writes those bytes (sites attempted
 // together are never nearest or diagonal neighbours: each 8x8 cell has a dead
 // row and column), so plain byte stores suffice.
@@ -42,8 +45,8 @@ constexpr int kCellsMax = (kMaxB / 8) * (kMaxB / 8);  // cells a workgroup holds
 constexpr int kSteps = 64;                             // C*C with C = 8
 constexpr int kMaxGroup = 64;                          // blocks per group (32 x 32)
 // LDS of a group: G tiles of (By + 1) x Bx bytes (one guard row each) with
-// G * Bx * By = 65536, plus 32 origin words per block.
-constexpr int kGroupLds = 65536 + kMaxGroup * 32 + kMaxGroup * 32 * 4;
+// G * Bx * By = 65536, plus 32 origin words and 3 placement words per block.
+constexpr int kGroupLds = 65536 + kMaxGroup * 32 + kMaxGroup * 32 * 4 + kMaxGroup * 3 * 4;
 
 // Acceptance modes: p = 1, q = 0 (pure growth); p and q each 0 or 1;
 // general p, q (per-attempt acceptance draws).
@@ -70,7 +73,9 @@ __device__ __forceinline__ Ctr4 philox10_dev(Ctr4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
-// 4 bits -> 4 bytes (bit j to bit 0 of byte j)
+// 4 bits -> 4 bytes (bit j to bit 0 of byte j): nib * (1 + 2^7 + 2^14 + 2^21)
+// puts bit j at positions j + 7i, all distinct (no carries); byte j keeps
+// i = j.
 __device__ __forceinline__ uint32_t spread4(uint32_t nib)
 {
     return __umul24(nib, 0x204081u) & 0x01010101u;
@@ -82,10 +87,11 @@ __device__ __forceinline__ uint32_t gather4(uint32_t bytes01, uint32_t w, uint32
     return __builtin_amdgcn_udot4(bytes01, w, acc, false);
 }
 
+// number of sigma_x = +1 bonds among the first n sites of a tile row
 __device__ __forceinline__ int row_prefix_bx(const uint8_t *row, int n)
 {
     int c = 0;
-    for (int u = 0; u < n; ++u) c += row[u] & 1;
+    for (int u = 0; u < n; ++u) c += (row[u] & 1) ^ 1;
     return c;
 }
 
@@ -105,7 +111,8 @@ __host__ __device__ inline int group_size(int Bx, int By, int nblk)
 //   kFixedB = 256: 256 x 256 blocks, G = 1, static geometry (the three LDS
 //                  addresses of an attempt are one register plus offsets);
 //   kFixedB = 0:   any block sides 32..256, geometry from `a`.
-// smem: at least G * (By + 1) * Bx bytes; opk: G * 32 words of LDS.
+// smem: at least G * (By + 1) * Bx bytes; opk: G * 35 words of LDS (origins,
+// then the blocks' placement when kFixedB = 0).
 template <int kThreads, int kMode, int kFixedB>
 __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const int G,
                                             uint8_t *__restrict__ smem, uint32_t *opk)
@@ -132,17 +139,41 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         opk[e] = (r.x >> 29) | ((r.y >> 29) << 3) | ((r.z >> 29) << 6) | ((r.w >> 29) << 9);
     }
 
+    // ---- block placement -------------------------------------------------
+    // Block bid = b0 + g starts at lattice site (sx + bi Bx, sy + bj By); that
+    // column sits at stored column xs of the source copy.  Per block: xs, the
+    // first row and bi (the block's word column in the destination copy).
+    const int lwpr = ilog2((uint32_t)wpr), lby = ilog2((uint32_t)By);
+    auto place = [&](int g, int &xs, int &y0, int &bi) {
+        const int bid = b0 + g;
+        bi = bid % a.nbx;
+        const int bj = bid / a.nbx;
+        xs = a.sx + bi * Bx - a.ox_src;
+        if (xs < 0) xs += a.Lx;
+        y0 = a.sy + bj * By;
+    };
+    int fxs = 0, fy0 = 0, fbi = 0;
+    int *geo = reinterpret_cast<int *>(opk + G * 32);
+    if (kFixedB) {
+        place(0, fxs, fy0, fbi);
+    } else {
+        for (int g = tid; g < G; g += kThreads) {
+            int xs, y0, bi;
+            place(g, xs, y0, bi);
+            geo[3 * g] = xs;
+            geo[3 * g + 1] = y0;
+            geo[3 * g + 2] = bi;
+        }
+        __syncthreads();
+    }
+
     // ---- HBM -> LDS with periodic wrap, bits -> bytes ---------------------
     for (int e = tid; e < G * By * wpr; e += kThreads) {
-        const int k = e % wpr;
-        const int rest = e / wpr;
-        const int v = rest % By;
-        const int g = rest / By;
-        const int bid = b0 + g;
-        const int bi = bid % a.nbx, bj = bid / a.nbx;
-        const int x0 = (a.sx + bi * Bx) % a.Lx;
-        const int xs = (x0 - a.ox_src + a.Lx) % a.Lx;
-        int y = a.sy + bj * By + v;
+        const int k = e & (wpr - 1);
+        const int v = (e >> lwpr) & (By - 1);
+        const int g = kFixedB ? 0 : (e >> (lwpr + lby));
+        const int xs = kFixedB ? fxs : geo[3 * g];
+        int y = (kFixedB ? fy0 : geo[3 * g + 1]) + v;
         if (y >= a.Ly) y -= a.Ly;
         int gw = (xs >> 5) + k;
         if (gw >= a.W) gw -= a.W;
@@ -150,17 +181,21 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         if (gw1 == a.W) gw1 = 0;
         const uint32_t off = (uint32_t)(xs & 31);
         const uint32_t *r0 = a.src + (size_t)y * a.W;
-        const uint32_t *r1 = a.src + ((size_t)a.Ly + y) * a.W;
-        const uint32_t bxw = funnel(r0[gw1], r0[gw], off);
-        const uint32_t byw = funnel(r1[gw1], r1[gw], off);
-        const uint32_t dead = (v == 0) ? 0x04040404u : 0u;
+        const uint32_t *r1 = r0 + (size_t)a.Ly * a.W;
+        const uint32_t bxw = ~funnel(r0[gw1], r0[gw], off);  // nx bits
+        const uint32_t byw = ~funnel(r1[gw1], r1[gw], off);
         uint32_t d[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const uint32_t sx = spread4((bxw >> (4 * m)) & 15u);
-            const uint32_t sy = spread4((byw >> (4 * m)) & 15u);
-            const uint32_t sxy = sx + (sy << 1);  // bx in bit 0, by in bit 1
-            d[m] = sxy + (sxy << 3) + dead;        // copies in bits 3 and 4
+            // nx in bit 0, ny in bit 1 of each byte (the bit fields are
+            // disjoint, so OR composes them); copies in bits 3 and 4
+            const uint32_t sxy = spread4((bxw >> (4 * m)) & 15u) |
+                                 (__umul24((byw >> (4 * m)) & 15u, 0x408102u) & 0x02020202u);
+            d[m] = sxy | (sxy << 3);
+        }
+        if (v == 0) {  // row v = 0 is the block border (few waves take this)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) d[m] |= 0x04040404u;
         }
         if (k == 0) d[0] |= 4u;  // column u = 0 is the block border
         uint4 *dst = reinterpret_cast<uint4 *>(smem + g * tsz + (v + 1) * Bx + 32 * k);
@@ -201,7 +236,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         gj[j] = live ? (uint32_t)g : 0u;
         opreg[j] = opk[(live ? g : 0) * 32 + (tid & 31)];
     }
-    const uint32_t fixed_tbl = (a.Tp != 0 ? (1u << 3) : 0u) | (a.Tq != 0 ? (1u << 24) : 0u);
+    const uint32_t fixed_tbl = (a.Tp != 0 ? (1u << 24) : 0u) | (a.Tq != 0 ? (1u << 3) : 0u);
     (void)fixed_tbl;
 
     for (int gs = 0; gs < kSteps / 8; ++gs) {
@@ -213,6 +248,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             sw[j][0] = r.x; sw[j][1] = r.y; sw[j][2] = r.z; sw[j][3] = r.w;
         }
         uint32_t aw[kCpt][4];
+        uint32_t opv[kCpt];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = gs * 8 + e;
@@ -229,36 +265,49 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             uint32_t off[kCpt], sv[kCpt], lv[kCpt], dv[kCpt];
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
-                uint32_t op;
-                if (kFixedB || wave_in_block)
-                    op = (uint32_t)__builtin_amdgcn_readlane((int)opreg[j], k >> 1);
-                else
-                    op = opk[(gj[j] << 5) + (k >> 1)];
-                op >>= 6 * (e & 1);
+                if ((e & 1) == 0) {
+                    if (kFixedB || wave_in_block)
+                        opv[j] = (uint32_t)__builtin_amdgcn_readlane((int)opreg[j], k >> 1);
+                    else
+                        opv[j] = opk[(gj[j] << 5) + (k >> 1)];
+                }
+                const uint32_t op = opv[j] >> (6 * (e & 1));
                 const uint32_t ox = op & 7u, oy = (op >> 3) & 7u;
                 const uint32_t h16 = (e & 1) ? (sw[j][e >> 1] >> 16) : (sw[j][e >> 1] & 0xffffu);
-                const uint32_t i = __umul24(h16, 49u) >> 16;  // one of the 7x7 active sites
-                const uint32_t bq = __umul24(i, 37u) >> 8;    // i / 7
-                const uint32_t ur = ox + cxo[j] + (i - 7u * bq);
-                const uint32_t vr = oy + cyo[j] + bq;
+                // Active site i = floor(49 h / 2^16) of the 7 x 7 (row-major),
+                // split as i = 7 q + a without a division: with 7 h = q 2^16 + r,
+                // q = floor(7 h / 2^16) = i div 7 and a = floor(7 r / 2^16) = i mod 7.
                 if (kFixedB == 256) {
-                    // ((vr mod 256) << 8) | (ur mod 256) in one byte permute
-                    off[j] = __builtin_amdgcn_perm(vr, ur, 0x0C0C0400u);
+                    // Y = 7 h + (row base << 16) keeps r in its low half, so
+                    // bits 16..23 of Y and X are the row and the column mod
+                    // 256; one byte permute packs them into (row << 8) | column
+                    const uint32_t Y = __umul24(h16, 7u) + (cyo[j] << 16) + (oy << 16);
+                    const uint32_t X = __umul24(Y & 0xffffu, 7u) + (cxo[j] << 16) + (ox << 16);
+                    off[j] = __builtin_amdgcn_perm(Y, X, 0x0C0C0602u);
                 } else {
+                    const uint32_t m7 = __umul24(h16, 7u);          // q in bits 16.., r below
+                    const uint32_t a7 = __umul24(m7 & 0xffffu, 7u);  // a in bits 16..18
+                    const uint32_t ur = ox + cxo[j] + (a7 >> 16);
+                    const uint32_t vr = oy + cyo[j] + (m7 >> 16);
                     off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
                 }
                 sv[j] = smem[off[j] + Bx];
                 lv[j] = smem[off[j] + Bx - 1];
                 dv[j] = smem[off[j]];
+                // the loads zero-extend; keep the code generator from
+                // re-narrowing the bytes (it would add masking operations)
+                asm("" : "+v"(sv[j]), "+v"(lv[j]), "+v"(dv[j]));
             }
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
                 bool flip;
                 if (kMode == kGrowth) {
-                    // minimum: the site byte is exactly 0x1B (bx = by = 1 and
-                    // copies, not dead) and neither neighbour bit is set
-                    const uint32_t m = (lv[j] & 8u) | (dv[j] & ~8u);
-                    flip = (((m & 24u) | (sv[j] ^ 0x1Bu)) == 0u);
+                    // minimum: s == 0 (nx = ny = 0 and copies, not dead),
+                    // l & 8 (nx of the left bond) and d & 16 (ny of the lower
+                    // bond) set: (~l & 8) | (~d & 16) | s == 0, two bit
+                    // operations (truth table 0xAE: (~A & B) | C)
+                    const uint32_t t = __builtin_amdgcn_bitop3_b32(lv[j], 8u, sv[j], 0xAE);
+                    flip = (__builtin_amdgcn_bitop3_b32(dv[j], 16u, t, 0xAE) == 0u);
                 } else {
                     // bitwise mux c ? a : b (truth table 0xE4): bit 3 from l,
                     // bit 4 from d, the others from s
@@ -267,14 +316,14 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                     uint32_t tbl = fixed_tbl;
                     if (kDrawAccept) {
                         const uint32_t r = aw[j][e & 3];
-                        tbl = ((uint64_t)r < a.Tp ? (1u << 3) : 0u) |
-                              ((uint64_t)r < a.Tq ? (1u << 24) : 0u);
+                        tbl = ((uint64_t)r < a.Tp ? (1u << 24) : 0u) |
+                              ((uint64_t)r < a.Tq ? (1u << 3) : 0u);
                     }
                     flip = (tbl >> code) & 1u;
                 }
                 if (flip) {
-                    // a growth flip only ever turns 0x1B (minimum) into 0
-                    smem[off[j] + Bx] = (kMode == kGrowth) ? (uint8_t)0 : (uint8_t)(sv[j] ^ 0x1Bu);
+                    // a growth flip only ever turns 0 (minimum) into 0x1B
+                    smem[off[j] + Bx] = (kMode == kGrowth) ? (uint8_t)0x1Bu : (uint8_t)(sv[j] ^ 0x1Bu);
                     smem[off[j] + Bx - 1] = (uint8_t)(lv[j] ^ 0x09u);
                     smem[off[j]] = (uint8_t)(dv[j] ^ 0x12u);
                 }
@@ -290,13 +339,11 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
 
     // ---- LDS -> HBM: bytes -> bits, aligned into the other copy -----------
     for (int e = tid; e < G * By * wpr; e += kThreads) {
-        const int k = e % wpr;
-        const int rest = e / wpr;
-        const int v = rest % By;
-        const int g = rest / By;
-        const int bid = b0 + g;
-        const int bi = bid % a.nbx, bj = bid / a.nbx;
-        int y = a.sy + bj * By + v;
+        const int k = e & (wpr - 1);
+        const int v = (e >> lwpr) & (By - 1);
+        const int g = kFixedB ? 0 : (e >> (lwpr + lby));
+        const int bi = kFixedB ? fbi : geo[3 * g + 2];
+        int y = (kFixedB ? fy0 : geo[3 * g + 1]) + v;
         if (y >= a.Ly) y -= a.Ly;
         const uint4 *src = reinterpret_cast<const uint4 *>(smem + g * tsz + (v + 1) * Bx + 32 * k);
         const uint4 q0 = src[0], q1 = src[1];
@@ -313,8 +360,8 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             byw |= yb << (8 * b);
         }
         const size_t col = (size_t)bi * wpr + k;
-        a.dst[(size_t)y * a.W + col] = bxw;
-        a.dst[((size_t)a.Ly + y) * a.W + col] = byw;
+        a.dst[(size_t)y * a.W + col] = ~bxw;  // back to sigma = +1 bits
+        a.dst[((size_t)a.Ly + y) * a.W + col] = ~byw;
     }
 }
 

@@ -11,9 +11,12 @@ constexpr int kFinalThreads = 1024;
 
 __global__ __launch_bounds__(kRowThreads) void width_rows_kernel(LatticeView v, int64_t *rows)
 {
+    __shared__ uint32_t lut[256];
+    core::width_lut_build(lut);
+    __syncthreads();
     const int y = blockIdx.x * (kRowThreads / 64) + (threadIdx.x >> 6);
     if (y >= v.Ly) return;
-    core::width_row(v, y, threadIdx.x & 63, rows);
+    core::width_row(v, y, threadIdx.x & 63, lut, rows);
 }
 
 __global__ __launch_bounds__(kFinalThreads) void width_final_kernel(const int64_t *rows, int32_t Lx,

@@ -4,12 +4,13 @@
 //
 // h(x,y) = H0 + G(y) + P_y(x), with G(y) = sum_{k<y} sigma_y(0,k) and
 // P_y(x) = sum_{l<x} sigma_x(l,y).  width_row: one wavefront reads row y's
-// words once, coalesced, re-aligned to physical columns with a funnel shift;
-// each lane turns its word into a popcount, a wavefront prefix scan gives
-// every word's starting height, and the lane accumulates the word's exact
-// sum and sum of squares.  width_combine: one workgroup scans the column-0
-// sigma_y bits to get G(y) and combines the rows into 128-bit
-// S1' = sum (h - H0) and S2' = sum (h - H0)^2.
+// words once, re-aligned to physical columns with a funnel shift; each lane
+// takes four consecutive words, sums them chunk by chunk through a 256-entry
+// table of 8-site partial sums, a wavefront prefix scan of the segments'
+// height changes gives every segment's starting height, and the lane adds its
+// segment's exact sum and sum of squares.  width_combine: one workgroup
+// scans the column-0 sigma_y bits to get G(y) and combines the rows into
+// 128-bit S1' = sum (h - H0) and S2' = sum (h - H0)^2.
 #pragma once
 
 #include "okpz_internal.h"
@@ -17,11 +18,34 @@
 namespace okpz {
 namespace core {
 
-// Row y of lattice view v by one wavefront (lane = threadIdx.x & 63); lane 0
-// writes rows[y] = sum_x P, rows[Ly + y] = sum_x P^2, rows[2 Ly + y] = the
-// sigma_y bit at physical column 0.
-__device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane, int64_t *rows)
+// Table of 8-site chunks.  For a byte c (bit i = site i, sigma_i = +1 when
+// set) and the partial heights q_0 = 0, q_{i+1} = q_i + sigma_i, entry c holds
+// s2 = sum_{i<8} q_i^2 in bits 0..7, s1 = sum_{i<8} q_i in bits 8..15 and
+// d = q_8 in bits 16..23 (s1 and d as signed bytes).  A chunk whose first site
+// sits at height B then adds 8 B + s1 to the sum of heights and
+// 8 B^2 + 2 B s1 + s2 to the sum of squares.  Built by the whole workgroup;
+// the caller synchronises before use.
+__device__ __forceinline__ void width_lut_build(uint32_t *lut)
 {
+    for (int c = threadIdx.x; c < 256; c += blockDim.x) {
+        int32_t q = 0, s1 = 0, s2 = 0;
+        for (int i = 0; i < 8; ++i) {
+            s1 += q;
+            s2 += q * q;
+            q += ((c >> i) & 1) ? 1 : -1;
+        }
+        lut[c] = (uint32_t)s2 | ((uint32_t)(s1 & 0xff) << 8) | ((uint32_t)(q & 0xff) << 16);
+    }
+}
+
+// Row y of lattice view v by one wavefront (lane = threadIdx.x & 63), four
+// consecutive words per lane per pass; lane 0 writes rows[y] = sum_x P,
+// rows[Ly + y] = sum_x P^2, rows[2 Ly + y] = the sigma_y bit at physical
+// column 0.  lut: the chunk table in LDS.
+__device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
+                                         const uint32_t *lut, int64_t *rows)
+{
+    constexpr int kWpl = 4;
     const uint32_t *row = v.planes + (size_t)y * v.W;
     const int xs0 = (v.Lx - v.ox) % v.Lx;  // stored column of physical column 0
     const uint32_t off = (uint32_t)(xs0 & 31);
@@ -29,37 +53,48 @@ __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
 
     int64_t a1 = 0, a2 = 0;
     int32_t carry = 0;
-    for (int base = 0; base < v.W; base += 64) {
-        const int k = base + lane;
-        uint32_t word = 0;
-        int32_t d = 0;
-        if (k < v.W) {
-            int gw = gws + k;
-            if (gw >= v.W) gw -= v.W;
-            int gw1 = gw + 1;
-            if (gw1 == v.W) gw1 = 0;
-            word = __builtin_amdgcn_alignbit(row[gw1], row[gw], off);
-            d = 2 * __popc(word) - 32;
+    for (int base = 0; base < v.W; base += 64 * kWpl) {
+        const int k0 = base + lane * kWpl;
+        const int nw = max(0, min(kWpl, v.W - k0));  // words of this lane
+        // heights relative to the first site of the lane's segment
+        int32_t B = 0, S1 = 0, S2 = 0;
+        if (nw > 0) {
+            int g = gws + k0;
+            if (g >= v.W) g -= v.W;
+            uint32_t lo = row[g];
+#pragma unroll
+            for (int t = 0; t < kWpl; ++t) {
+                if (t < nw) {
+                    int g1 = g + 1;
+                    if (g1 == v.W) g1 = 0;
+                    const uint32_t hi = row[g1];
+                    const uint32_t word = __builtin_amdgcn_alignbit(hi, lo, off);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t e = lut[(word >> (8 * j)) & 255u];
+                        const int32_t s2 = (int32_t)(e & 0xffu);
+                        const int32_t s1 = (int32_t)(int8_t)(e >> 8);
+                        const int32_t d = (int32_t)(int8_t)(e >> 16);
+                        const int32_t t1 = 8 * B + s1;
+                        S1 += t1;
+                        S2 += B * (t1 + s1) + s2;
+                        B += d;
+                    }
+                    lo = hi;
+                    g = g1;
+                }
+            }
         }
-        int32_t incl = d;
+        int32_t incl = B;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int32_t t = __shfl_up(incl, o, 64);
             if (lane >= o) incl += t;
         }
-        const int32_t base_h = carry + incl - d;  // P_y at the word's first site
-        if (k < v.W) {
-            int32_t q = 0, s1 = 0, s2 = 0;
-#pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                s1 += q;
-                s2 += q * q;
-                q += (int32_t)((word >> i) & 1u) * 2 - 1;
-            }
-            const int64_t b = base_h;
-            a1 += 32 * b + s1;
-            a2 += 32 * b * b + 2 * b * s1 + s2;
-        }
+        const int64_t b = carry + incl - B;  // P_y at the segment's first site
+        const int64_t n = 32 * nw;
+        a1 += n * b + S1;
+        a2 += n * b * b + 2 * b * S1 + S2;
         carry += __shfl(incl, 63, 64);
     }
 #pragma unroll

@@ -92,8 +92,24 @@ _sig("okpz_batch_samples", ctypes.c_int, _vp, ctypes.c_int32, _i64p, _i64p, _i64
      ctypes.c_int32, _i32p)
 _sig("okpz_batch_get_lattice", ctypes.c_int, _vp, ctypes.c_int32, _u8p, _sz)
 _sig("okpz_batch_h0", ctypes.c_int, _vp, ctypes.c_int32, _i64p)
+_sig("okpz_batch_w2_histogram", ctypes.c_int, _vp, _i64, _i64, _i64, ctypes.c_double,
+     ctypes.c_double, ctypes.c_int32, _i64p, _i64p, _i64p)
 _sig("okpz_batch_free", ctypes.c_int, _vp)
 _sig("okpz_batch_last_error", ctypes.c_char_p)
+
+_sig("okpz_serve_create", ctypes.c_int, ctypes.POINTER(_vp), _sz, ctypes.c_int32, _i64,
+     ctypes.c_double)
+_sig("okpz_serve_set_mapping", ctypes.c_int, _vp, ctypes.c_int32, ctypes.c_int32)
+_sig("okpz_serve_now", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double))
+_sig("okpz_serve_submit", ctypes.c_int, _vp, _jobp, ctypes.c_double, ctypes.c_int32, _i64p)
+_sig("okpz_serve_step", ctypes.c_int, _vp, _i32p, _i32p)
+_sig("okpz_serve_job", ctypes.c_int, _vp, _i64, _i32p, ctypes.POINTER(ctypes.c_double),
+     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+_sig("okpz_serve_samples", ctypes.c_int, _vp, _i64, _i64p, _i64p, _i64p, ctypes.c_int32, _i32p)
+_sig("okpz_serve_result", ctypes.c_int, _vp, _i64, _u8p, _sz, _i64p)
+_sig("okpz_serve_stats", ctypes.c_int, _vp, _i64p, ctypes.POINTER(ctypes.c_double), _i64p,
+     ctypes.POINTER(_sz))
+_sig("okpz_serve_free", ctypes.c_int, _vp)
 
 EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on", "okpz_sweep",
             "okpz_width", "okpz_w2", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
@@ -101,6 +117,9 @@ EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_free", "okpz_last_error", "okpz_batch_create", "okpz_batch_set_mapping",
             "okpz_batch_get_mapping", "okpz_batch_autotune", "okpz_batch_run",
             "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
+            "okpz_batch_w2_histogram", "okpz_serve_create", "okpz_serve_set_mapping",
+            "okpz_serve_now", "okpz_serve_submit", "okpz_serve_step", "okpz_serve_job",
+            "okpz_serve_samples", "okpz_serve_result", "okpz_serve_stats", "okpz_serve_free",
             "okpz_batch_free", "okpz_batch_last_error"]
 
 
@@ -300,6 +319,15 @@ class Batch:
         _bcheck(_lib.okpz_batch_h0(self._h, job, ctypes.byref(v)))
         return v.value
 
+    def w2_histogram(self, Lx: int, Ly: int, t_from: int, lo: float, hi: float, nbins: int):
+        """(counts, under, over) of the W^2 samples with t >= t_from of size Lx x Ly."""
+        counts = np.zeros(nbins, dtype=np.int64)
+        u, o = ctypes.c_int64(), ctypes.c_int64()
+        _bcheck(_lib.okpz_batch_w2_histogram(self._h, Lx, Ly, t_from, float(lo), float(hi), nbins,
+                                             counts.ctypes.data_as(_i64p), ctypes.byref(u),
+                                             ctypes.byref(o)))
+        return counts, u.value, o.value
+
     def free(self) -> None:
         if self._h:
             _bcheck(_lib.okpz_batch_free(self._h))
@@ -326,4 +354,119 @@ def sampling_times(t_max: int, m: float) -> list:
             out.append(c)
     if t_max > 0 and (not out or out[-1] != t_max):
         out.append(int(t_max))
+    return out
+
+
+class Server:
+    """Continuous batching of simulation jobs (see okpz_serve_* in okpz.h)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 64, quantum_sites: int = 1 << 28,
+                 m: float = 0.01):
+        h = _vp()
+        _bcheck(_lib.okpz_serve_create(ctypes.byref(h), int(hbm_budget), int(max_slots),
+                                       int(quantum_sites), float(m)))
+        self._h = h
+        self.jobs = {}
+
+    def set_mapping(self, threads: int, workgroups: int = 0) -> None:
+        _bcheck(_lib.okpz_serve_set_mapping(self._h, int(threads), int(workgroups)))
+
+    def now(self) -> float:
+        v = ctypes.c_double()
+        _bcheck(_lib.okpz_serve_now(self._h, ctypes.byref(v)))
+        return v.value
+
+    def submit(self, job, arrival: float = -1.0, keep_lattice: bool = False) -> int:
+        Lx, Ly, p, q, seed, t_max = job
+        j = OkpzJob(int(Lx), int(Ly), float(p), float(q), int(seed), int(t_max))
+        i = ctypes.c_int64()
+        _bcheck(_lib.okpz_serve_submit(self._h, ctypes.byref(j), float(arrival), int(keep_lattice),
+                                       ctypes.byref(i)))
+        self.jobs[i.value] = tuple(job)
+        return i.value
+
+    def step(self) -> tuple:
+        r, w = ctypes.c_int32(), ctypes.c_int32()
+        _bcheck(_lib.okpz_serve_step(self._h, ctypes.byref(r), ctypes.byref(w)))
+        return r.value, w.value
+
+    def job(self, i: int) -> dict:
+        st = ctypes.c_int32()
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _bcheck(_lib.okpz_serve_job(self._h, i, ctypes.byref(st), ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)))
+        return {"state": st.value, "arrival": a.value, "admit": b.value, "finish": c.value}
+
+    def samples(self, i: int):
+        n = ctypes.c_int32()
+        _bcheck(_lib.okpz_serve_samples(self._h, i, None, None, None, 0, ctypes.byref(n)))
+        t = np.zeros(n.value, dtype=np.int64)
+        s1 = np.zeros(n.value, dtype=np.int64)
+        s2 = np.zeros(n.value, dtype=np.int64)
+        _bcheck(_lib.okpz_serve_samples(self._h, i, t.ctypes.data_as(_i64p),
+                                        s1.ctypes.data_as(_i64p), s2.ctypes.data_as(_i64p),
+                                        n.value, ctypes.byref(n)))
+        return t, s1, s2
+
+    def result(self, i: int, lattice: bool = False):
+        Lx, Ly = self.jobs[i][0], self.jobs[i][1]
+        h0 = ctypes.c_int64()
+        if lattice:
+            out = np.empty((Ly, Lx), dtype=np.uint8)
+            _bcheck(_lib.okpz_serve_result(self._h, i, out.ctypes.data_as(_u8p), out.nbytes,
+                                           ctypes.byref(h0)))
+            return out, h0.value
+        _bcheck(_lib.okpz_serve_result(self._h, i, None, 0, ctypes.byref(h0)))
+        return None, h0.value
+
+    def stats(self) -> dict:
+        q, d, b = ctypes.c_int64(), ctypes.c_int64(), _sz()
+        ms = ctypes.c_double()
+        _bcheck(_lib.okpz_serve_stats(self._h, ctypes.byref(q), ctypes.byref(ms), ctypes.byref(d),
+                                      ctypes.byref(b)))
+        return {"quanta": q.value, "device_ms": ms.value, "done": d.value, "bytes": b.value}
+
+    def drain(self, timeout_s: float = 600.0) -> None:
+        """Run quanta until every submitted job is done (sleeping until the
+        next arrival when nothing is resident)."""
+        import time
+
+        t_end = self.now() + timeout_s
+        while True:
+            running, waiting = self.step()
+            if running == 0 and waiting == 0:
+                return
+            if running == 0:
+                nxt = min(self.job(i)["arrival"] for i in self.jobs if self.job(i)["state"] == 0)
+                time.sleep(max(0.0, min(0.05, nxt - self.now())))
+            if self.now() > t_end:
+                raise TimeoutError("serving did not drain in time")
+
+    def free(self) -> None:
+        if self._h:
+            _bcheck(_lib.okpz_serve_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def job_stream(n: int, rate: float, seed: int, sizes=(64, 8192), t_range=(1000, 10000)):
+    """Synthetic served job stream: Poisson arrivals at `rate` jobs/s; L a
+    power of two log-uniform in `sizes`; p uniform in [0.6, 1]; q = 0 or
+    1 - p with probability 1/2; t_max log-uniform in `t_range`; job seed =
+    index + 1.  Returns [(arrival_s, (L, L, p, q, seed, t_max)), ...]."""
+    rng = np.random.default_rng(seed)
+    lo, hi = int(np.log2(sizes[0])), int(np.log2(sizes[1]))
+    t, out = 0.0, []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        L = 1 << int(rng.integers(lo, hi + 1))
+        p = float(rng.uniform(0.6, 1.0))
+        q = 0.0 if rng.random() < 0.5 else 1.0 - p
+        tm = int(round(np.exp(rng.uniform(np.log(t_range[0]), np.log(t_range[1])))))
+        out.append((t, (L, L, p, q, i + 1, tm)))
     return out

@@ -1,0 +1,87 @@
+"""Serving with continuous batching: jobs arriving while others run are
+admitted at quantum boundaries as slots and bytes free up; every job's
+result is bit for bit the one it gives alone."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def okpz():
+    from paper_1110_6745_amd import okpz as m
+
+    return m
+
+
+def alone(okpz, job, m):
+    Lx, Ly, p, q, seed, t_max = job
+    sim = okpz.okpz_init(Lx, Ly, p, q, seed)
+    ref = [(t,) + sim.width(t) for t in okpz.sampling_times(t_max, m)]
+    lat, h0 = sim.get_lattice(), sim.h0()
+    sim.free()
+    return ref, lat, h0
+
+
+def test_mix_equals_alone_with_staggered_arrivals(okpz):
+    m = 0.2
+    jobs = [(64, 64, 1.0, 0.0, 1, 40), (256, 256, 0.95, 0.05, 2, 25), (32, 32, 0.7, 0.3, 3, 60),
+            (512, 512, 1.0, 0.0, 4, 10), (128, 128, 0.6, 0.4, 5, 30), (96, 96, 1.0, 0.0, 6, 0),
+            (1024, 1024, 0.8, 0.0, 7, 6), (64, 64, 1.0, 0.0, 8, 33)]
+    sv = okpz.Server(hbm_budget=1 << 30, max_slots=3, quantum_sites=1 << 18, m=m)
+    ids = [sv.submit(j, arrival=0.002 * k, keep_lattice=True) for k, j in enumerate(jobs)]
+    sv.drain()
+    st = sv.stats()
+    assert st["done"] == len(jobs) and st["bytes"] == 0 and st["quanta"] > 3
+    for i, job in zip(ids, jobs):
+        ref, lat, h0 = alone(okpz, job, m)
+        t, s1, s2 = sv.samples(i)
+        assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref, f"job {job}"
+        got, gh0 = sv.result(i, lattice=True)
+        assert np.array_equal(got, lat) and gh0 == h0, f"job {job}"
+        info = sv.job(i)
+        assert info["state"] == 2 and info["admit"] >= info["arrival"] and info["finish"] >= info["admit"]
+    sv.free()
+
+
+def test_admission_respects_slots_and_bytes(okpz):
+    # budget fits exactly two 512^2 jobs: never more than two are resident
+    per = okpz.okpz_required_bytes(512, 512)
+    sv = okpz.Server(hbm_budget=int(2.2 * per), max_slots=8, quantum_sites=1 << 16, m=1.0)
+    ids = [sv.submit((512, 512, 1.0, 0.0, 10 + k, 8)) for k in range(5)]
+    peak = 0
+    while True:
+        running, waiting = sv.step()
+        peak = max(peak, running)
+        if running == 0 and waiting == 0:
+            break
+    assert peak <= 2
+    assert all(sv.job(i)["state"] == 2 for i in ids)
+    # admissions happen in arrival (submission) order
+    admits = [sv.job(i)["admit"] for i in ids]
+    assert admits == sorted(admits)
+    sv.free()
+
+
+def test_job_too_big_for_budget_is_refused(okpz):
+    # a 1024^2 job holds two 256 KiB lattice copies: more than a 512 KiB budget
+    sv = okpz.Server(hbm_budget=1 << 19, max_slots=2, quantum_sites=1 << 16, m=1.0)
+    with pytest.raises(okpz.OkpzError) as e:
+        sv.submit((1024, 1024, 1.0, 0.0, 1, 5))
+    assert e.value.code == okpz.OKPZ_EBUSY
+    sv.free()
+
+
+def test_poisson_stream_small(okpz):
+    stream = okpz.job_stream(24, rate=200.0, seed=3, sizes=(32, 256), t_range=(20, 200))
+    sv = okpz.Server(hbm_budget=1 << 30, max_slots=8, quantum_sites=1 << 20, m=0.5)
+    ids = [sv.submit(job, arrival=a) for a, job in stream]
+    sv.drain()
+    for i in ids[:6]:
+        ref, _, h0 = alone(okpz, sv.jobs[i], 0.5)
+        t, s1, s2 = sv.samples(i)
+        assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref
+        assert sv.result(i)[1] == h0
+    lat = [sv.job(i)["finish"] - sv.job(i)["arrival"] for i in ids]
+    assert min(lat) >= 0
+    sv.free()
