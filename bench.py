@@ -23,6 +23,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# HBM bytes per sweep launch at 2^17 x 2^17 from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy
+# (profiles/sweep_kernel_L131072_hbm_counters.md).  Reported only while the
+# sweep sources hash to the value the counters were taken on.
+TRAFFIC_MEASURED = {"sources_sha256_16": "b4f961e9ccaf3fb3", "L": 1 << 17, "bytes": 8.625e9}
+SWEEP_SOURCES = ("sweep_core.h", "sweep.hip", "okpz_internal.h")
 METRIC = "site updates/s (+% HBM roofline) at L=2^17; realizations/s batched vs plain; serving p50/p99"
 
 
@@ -160,6 +166,16 @@ def serve_leg(n_jobs=64, rate=50.0, seed=7, capacity=None):
     return out
 
 
+def sweep_sources_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1110_6745_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -229,6 +245,9 @@ def main():
     value = N * args.steps / elapsed
     achieved_gbs = 0.5 * N / (sweep_ms * 1e-3) / 1e9
     w2 = [(t, (N * s2 - s1 * s1) / (N * N)) for t, s1, s2 in widths]
+    traffic = None
+    if L == TRAFFIC_MEASURED["L"] and sweep_sources_hash() == TRAFFIC_MEASURED["sources_sha256_16"]:
+        traffic = TRAFFIC_MEASURED["bytes"]
 
     out = {
         "metric": METRIC,
@@ -250,7 +269,7 @@ def main():
         "sweep_kernel_ms": sweep_ms,
         "sweep_site_updates_per_s": N / (sweep_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
         "w2_last": w2[-1] if w2 else None,
     }
     sim.free()
