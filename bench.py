@@ -140,7 +140,7 @@ def serve_leg(n_jobs=64, rate=50.0, seed=7, capacity=None):
     def one(r):
         stream = okpz.job_stream(n_jobs, r, seed)
         work = sum(L * L * t for _, (L, _, _, _, _, t) in stream)
-        sv = okpz.Server(hbm_budget=64 << 30, max_slots=64, quantum_sites=1 << 28, m=0.01)
+        sv = okpz.Server(hbm_budget=64 << 30, max_slots=64, quantum_sites=1 << 31, m=0.01)
         t0 = sv.now() + 0.05
         ids = [sv.submit(job, t0 + a) for a, job in stream]
         sv.drain(timeout_s=300.0)

@@ -188,9 +188,11 @@ const char *okpz_batch_last_error(void);
  * okpz_serve_step is one quantum: arrived jobs are admitted in arrival order
  * while a slot is free and their device bytes fit hbm_budget (their lattices
  * then stay resident until they finish); one persistent launch advances every
- * resident job by about quantum_sites site updates (at least one MCS), all
- * jobs' work interleaved on the device; finished jobs are retired and their
- * memory freed.  Results are bit for bit those of the job run alone.
+ * resident job by its share of MCS, all jobs' work interleaved on the device;
+ * finished jobs are retired and their memory freed.  A quantum lasts about
+ * quantum_sites / 1e12 seconds; a job's share is the number of its sweeps
+ * (at least one) that fit that time, a sweep of an L x L lattice counted as
+ * 20 us + L^2 / 1e12 s.  Results are bit for bit those of the job run alone. 
  * ---------------------------------------------------------------------- */
 typedef struct okpz_server okpz_server; /* opaque */
 

@@ -2,12 +2,13 @@
 // each with its own p, q, seed and length, run to completion in ONE
 // persistent launch (ensembles of independent runs, Sec. III and IV).
 //
-// Work item = (job, group of blocks) of the job's current sweep.  Each job
-// has a claim word (sweep << 32 | next group); a resident workgroup's first
-// wavefront scans the claim words, 64 jobs per load, and claims a group of a
-// job with one fetch-and-add on that job's word, so contention is spread
-// over the jobs.  The workgroup that completes the last group of a job's
-// sweep advances the job (time, stored offset, lattice copy), measures the
+// Work item = (job, chunk of groups of blocks) of the job's current sweep
+// (one group per item for lattices up to 2048 x 2048; larger lattices hand
+// out at most 128 items per sweep).  Each job has a claim word (sweep << 32 |
+// next item); a resident workgroup's first wavefront scans the claim words,
+// 64 jobs per load, and claims an item of a job with one fetch-and-add on
+// that job's word, so contention is spread over the jobs.  The workgroup that
+// completes the last item of a job's sweep advances the job (time, stored offset, lattice copy), measures the
 // exact width when a sampling time is reached, and reopens the job's claim
 // word for the next sweep.  No workgroup ever waits for a particular other
 // workgroup, so the launch needs no co-residency; a workgroup that finds no
@@ -48,6 +49,8 @@ struct JobDesc {
     const int32_t *sample_t;
     int32_t nsamp;
     int32_t Lx, Ly, W, Bx, By, nbx, nby, G, ngroups, mode;
+    int32_t chunk;   // groups per work item
+    int32_t nitems;  // work items per sweep
     int32_t t_max;
     uint32_t k0, k1;
     uint64_t Tp, Tq;
@@ -63,22 +66,25 @@ struct JobState {
 };
 
 struct Control {
-    uint64_t progress;  // groups completed by the whole launch
+    uint64_t progress;  // sweeps completed by the whole launch
     int32_t finished;   // jobs that reached their stop target
     int32_t error;      // 1: watchdog
 };
 
-// claim[r] = (sweep << 32) | next group to hand out; job r has an open group
-// while the low word is below ngroups[r].  A finished or empty job holds
+// claim[r] = (sweep << 32) | next item to hand out; job r has an open item
+// while the low word is below ngr[r] (its items per sweep).  A finished or empty job holds
 // kClosed in the low word.  A scan can see a word open that is exhausted or
 // closed by the time the wave's fetch-and-add lands; such late increments
 // are at most one per workgroup per word value, so the low word never
 // carries into the sweep number (kClosed + workgroups < 2^32).
 constexpr uint32_t kClosed = 0x80000000u;
 
+// Polled words (claim words, counters) are read and published at system
+// scope, which bypasses the per-XCD caches: a poller never spins on a stale
+// line.
 __device__ __forceinline__ uint64_t ld_rlx(uint64_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ inline SweepLaunch make_launch(const JobDesc &jd, const JobState &js)
@@ -125,14 +131,16 @@ __device__ __forceinline__ void run_group(const SweepLaunch &a, int b0, int G, u
 // the job's state for the new sweep has been written.
 __device__ void publish(const JobDesc &jd, const JobState &ns, Control *ctl, uint64_t *claim, int r)
 {
+    // one completed sweep: the watchdog's sign of life
+    __hip_atomic_fetch_add(&ctl->progress, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ns.s >= jd.t_max) {
         __hip_atomic_store(&claim[r], ((uint64_t)ns.s << 32) | kClosed, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+                           __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_fetch_add(&ctl->finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    __atomic_thread_fence(__ATOMIC_RELEASE);  // state and lattice before the claim word
-    __hip_atomic_store(&claim[r], (uint64_t)ns.s << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // state and lattice before the claim word
+    __hip_atomic_store(&claim[r], (uint64_t)ns.s << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Wave 0 looks for a job with an open group and claims one.  Returns the
@@ -191,14 +199,17 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
             if (r >= 0) start = r;  // every lane scans from the same place next time
             if (tid == 0) {
                 if (r >= 0) {
-                    __atomic_thread_fence(__ATOMIC_ACQUIRE);  // the job's state and lattice
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the job's state and lattice
                     idle = 0;
-                } else if (__hip_atomic_load(&ctl->finished, __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT) >= njobs ||
+                } else if (__hip_atomic_load(&ctl->finished, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_SYSTEM) >= njobs ||
                            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                             __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
                     r = -1;
                 } else {
+                    // nothing open: retry after a short sleep, unless no sweep
+                    // has completed anywhere for idle_limit probes
+                    r = -2;
                     const uint64_t p = ld_rlx(&ctl->progress);
                     if (p != seen) {
                         seen = p;
@@ -207,10 +218,7 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
                         __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         r = -1;
                     }
-                    if (r != -1) {
-                        r = -2;
-                        __builtin_amdgcn_s_sleep(16);
-                    }
+                    if (r == -2) __builtin_amdgcn_s_sleep(16);
                 }
                 s_job = r;
                 s_claim = w;
@@ -223,27 +231,29 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
         if (r == -1) break;
         if (r == -2) continue;
 
-        const int gi = (int)(uint32_t)w;
+        const int item = (int)(uint32_t)w;
         const JobDesc jd = jobs[r];
         const JobState js = state[r];
         const SweepLaunch a = make_launch(jd, js);
-        const int b0 = gi * jd.G;
-        const int Gc = min(jd.G, jd.nbx * jd.nby - b0);
-        if (jd.mode == core::kGrowth)
-            run_group<kThreads, core::kGrowth>(a, b0, Gc, smem);
-        else if (jd.mode == core::kFixed)
-            run_group<kThreads, core::kFixed>(a, b0, Gc, smem);
-        else
-            run_group<kThreads, core::kDraw>(a, b0, Gc, smem);
-        __syncthreads();
+        const int g_end = min(jd.ngroups, (item + 1) * jd.chunk);
+        for (int gi = item * jd.chunk; gi < g_end; ++gi) {
+            const int b0 = gi * jd.G;
+            const int Gc = min(jd.G, jd.nbx * jd.nby - b0);
+            if (jd.mode == core::kGrowth)
+                run_group<kThreads, core::kGrowth>(a, b0, Gc, smem);
+            else if (jd.mode == core::kFixed)
+                run_group<kThreads, core::kFixed>(a, b0, Gc, smem);
+            else
+                run_group<kThreads, core::kDraw>(a, b0, Gc, smem);
+            __syncthreads();  // the group's tile is reused by the next group
+        }
 
         if (tid == 0) {
             s_width = 0;
-            __hip_atomic_fetch_add(&ctl->progress, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // release this group's lattice words; the last group acquires all
+            // release this item's lattice words; the last item acquires all
             const uint32_t d = __hip_atomic_fetch_add(&state[r].done, 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (d == (uint32_t)jd.ngroups) {  // last group of sweep s: advance the job
+            if (d == (uint32_t)jd.nitems) {  // last item of sweep s: advance the job
                 JobState ns = js;
                 ns.s = js.s + 1;
                 ns.ox = a.sx;
@@ -386,6 +396,18 @@ std::vector<int32_t> sample_times(int64_t t_max, double m)
 size_t al(size_t n) { return (n + 255) / 256 * 256; }
 
 // (Re)start every job from the flat state with the given sweep limit.
+// Work items of a sweep: a claim (one atomic on the job's claim word) and a
+// completion count each, so a large lattice hands out its groups in chunks:
+// one atomic on one word takes about a microsecond, far longer than a
+// group's share of a sweep on a full device.
+constexpr int kItemsPerSweep = 1024;
+
+void set_items(JobDesc &d)
+{
+    d.chunk = std::max(1, (d.ngroups + kItemsPerSweep - 1) / kItemsPerSweep);
+    d.nitems = (d.ngroups + d.chunk - 1) / d.chunk;
+}
+
 int reset(okpz_batch *b, const std::vector<int32_t> &tmax)
 {
     const int n = (int)b->jobs.size();
@@ -401,7 +423,7 @@ int reset(okpz_batch *b, const std::vector<int32_t> &tmax)
         int ns = 0;
         while (ns < (int)b->times[r].size() && b->times[r][ns] <= tmax[r]) ++ns;
         desc[r].nsamp = ns;
-        ngr[r] = desc[r].ngroups;
+        ngr[r] = desc[r].nitems;
         if (desc[r].t_max == 0) {
             claim[r] = okpz::batch::kClosed;
             ++finished;
@@ -547,6 +569,7 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
         d.nby = nby;
         d.G = G;
         d.ngroups = (nbx * nby + G - 1) / G;
+        set_items(d);
         d.k0 = (uint32_t)(j.seed & 0xffffffffu);
         d.k1 = (uint32_t)(j.seed >> 32);
         d.Tp = okpz::threshold_of(j.p);
@@ -802,11 +825,16 @@ const char *okpz_batch_last_error(void) { return b_err.c_str(); }
 // lattices are allocated and stay resident until they finish); then one
 // persistent launch advances every resident job by its quantum share of
 // sweeps, all jobs' groups interleaved on the device; finished jobs are
-// retired (samples copied out, memory freed) and their latency recorded.  A
-// job's share is about quantum_sites site updates (at least one sweep;
-// lattices below 512 x 512 are counted as 512 x 512 so that a small job's
-// sequential sweeps do not stretch the quantum).  A job's results do not
-// depend on when it ran or with which other jobs.
+// retired (samples copied out, memory freed) and their latency recorded.
+//
+// Shares: a quantum lasts about T = quantum_sites / kNominalRate seconds.
+// The sweeps of one job form a sequential chain, each taking about
+// kSweepLatency + L^2 / kNominalRate seconds (a small lattice is latency
+// bound, a large one throughput bound), so a job's share is the number of
+// sweeps its chain completes in T (at least one).  Large jobs then keep the
+// device busy while small jobs' chains run beside them, and no small job
+// stretches the quantum.  A job's results do not depend on when it ran or
+// with which other jobs.
 #include <chrono>
 #include <deque>
 
@@ -836,6 +864,13 @@ size_t job_bytes(const okpz_job &j, size_t nsamp)
 }
 
 }  // namespace
+
+// Device model behind the quantum shares: site updates per second of the
+// whole device on one large lattice, and the time of one sweep of a lattice
+// that fits one workgroup (staging, 64 barrier-separated steps, store and
+// the hand-over to the next sweep).
+constexpr double kNominalRate = 1.0e12;
+constexpr double kSweepLatency = 2.0e-5;
 
 struct okpz_server {
     size_t budget = 0, used = 0;
@@ -916,6 +951,7 @@ int admit(okpz_server *sv, ServeJob &J, int slot, double t)
     d.nby = (int32_t)(j.Ly / g.By);
     d.G = okpz::core::group_size(g.Bx, g.By, d.nbx * d.nby);
     d.ngroups = (d.nbx * d.nby + d.G - 1) / d.G;
+    set_items(d);
     d.k0 = (uint32_t)(j.seed & 0xffffffffu);
     d.k1 = (uint32_t)(j.seed >> 32);
     d.Tp = okpz::threshold_of(j.p);
@@ -1085,13 +1121,14 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
             continue;
         }
         ServeJob &J = sv->jobs[k];
-        const int64_t L2 = std::max<int64_t>(J.job.Lx * J.job.Ly, 512 * 512);
-        const int64_t share = std::max<int64_t>(1, sv->quantum_sites / L2);
+        const double quantum_s = (double)sv->quantum_sites / kNominalRate;
+        const double sweep_s = kSweepLatency + (double)(J.job.Lx * J.job.Ly) / kNominalRate;
+        const int64_t share = std::max<int64_t>(1, (int64_t)(quantum_s / sweep_s));
         const int64_t stop = std::min<int64_t>(J.job.t_max, J.s + share);
         desc[i] = J.desc;
         desc[i].t_max = (int32_t)stop;
         claim[i] = (uint64_t)J.s << 32;
-        ngr[i] = J.desc.ngroups;
+        ngr[i] = J.desc.nitems;
         ++active;
     }
     if (running) *running = active;

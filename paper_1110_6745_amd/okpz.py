@@ -360,7 +360,7 @@ def sampling_times(t_max: int, m: float) -> list:
 class Server:
     """Continuous batching of simulation jobs (see okpz_serve_* in okpz.h)."""
 
-    def __init__(self, hbm_budget: int, max_slots: int = 64, quantum_sites: int = 1 << 28,
+    def __init__(self, hbm_budget: int, max_slots: int = 64, quantum_sites: int = 1 << 31,
                  m: float = 0.01):
         h = _vp()
         _bcheck(_lib.okpz_serve_create(ctypes.byref(h), int(hbm_budget), int(max_slots),
