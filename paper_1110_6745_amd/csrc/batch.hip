@@ -72,7 +72,7 @@ struct Control {
 };
 
 // claim[r] = (sweep << 32) | next item to hand out; job r has an open item
-// while the low word is below ngr[r] (its items per sweep).  A finished or empty job holds
+// while the low word is below nitems[r] (its items per sweep).  A finished or empty job holds
 // kClosed in the low word.  A scan can see a word open that is exhausted or
 // closed by the time the wave's fetch-and-add lands; such late increments
 // are at most one per workgroup per word value, so the low word never
@@ -143,35 +143,39 @@ __device__ void publish(const JobDesc &jd, const JobState &ns, Control *ctl, uin
     __hip_atomic_store(&claim[r], (uint64_t)ns.s << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Wave 0 looks for a job with an open group and claims one.  Returns the
-// job index and writes the claimed (sweep << 32 | group), or -1.
-__device__ int find_and_claim(uint64_t *claim, const int32_t *ngr, int njobs, int start,
-                              uint64_t *got)
+// Wave 0 looks for an open item and claims one, trying jobs in priority
+// order (order[0] first).  Returns the job index and writes the claimed
+// (sweep << 32 | item), or -1.
+__device__ int find_and_claim(uint64_t *claim, const int32_t *nitems, const int32_t *order,
+                              int njobs, uint64_t *got)
 {
     const int lane = threadIdx.x & 63;
     for (int base = 0; base < njobs; base += 64) {
-        int r = start + base + lane;
-        if (r >= njobs) r -= njobs;
-        if (r >= njobs) r -= njobs;
+        const int idx = base + lane;
+        const int r = idx < njobs ? order[idx] : 0;
         bool open = false;
-        if (base + lane < njobs) {
+        if (idx < njobs) {
             const uint64_t w = ld_rlx(&claim[r]);
-            open = (uint32_t)w < (uint32_t)ngr[r];
+            open = (uint32_t)w < (uint32_t)nitems[r];
         }
         uint64_t mask = __ballot(open);
         while (mask) {
-            const int pick = __ffsll((unsigned long long)mask) - 1;
+            // spread workgroups over the open jobs of this window (the
+            // window holds the highest-priority jobs still open)
+            uint64_t m = mask;
+            for (int k = (int)(blockIdx.x % (unsigned)__popcll(mask)); k > 0; --k) m &= m - 1;
+            const int pick = __ffsll((unsigned long long)m) - 1;
             const int rr = __shfl(r, pick, 64);
             uint64_t w = 0;
             if (lane == 0)
                 w = __hip_atomic_fetch_add(&claim[rr], (uint64_t)1, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
             w = __shfl(w, 0, 64);
-            if ((uint32_t)w < (uint32_t)ngr[rr]) {
+            if ((uint32_t)w < (uint32_t)nitems[rr]) {
                 *got = w;
                 return rr;
             }
-            mask &= mask - 1;  // that job ran out meanwhile; try the next one
+            mask &= ~(1ull << pick);  // that job ran out meanwhile; try another one
         }
     }
     return -1;
@@ -180,7 +184,7 @@ __device__ int find_and_claim(uint64_t *claim, const int32_t *ngr, int njobs, in
 template <int kThreads>
 __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, JobState *state,
                                                          Control *ctl, uint64_t *claim,
-                                                         const int32_t *ngr, int32_t njobs,
+                                                         const int32_t *sched, int32_t njobs,
                                                          uint64_t idle_limit)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -190,13 +194,12 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
     __shared__ int64_t s_out[4];
     const int tid = threadIdx.x;
     uint64_t idle = 0, seen = 0;
-    int start = (int)((blockIdx.x * 61u) % (uint32_t)njobs);
+    const int32_t *nitems = sched, *order = sched + njobs;
 
     while (true) {
         if (tid < 64) {
             uint64_t w = 0;
-            int r = find_and_claim(claim, ngr, njobs, start, &w);  // uniform over wave 0
-            if (r >= 0) start = r;  // every lane scans from the same place next time
+            int r = find_and_claim(claim, nitems, order, njobs, &w);  // uniform over wave 0
             if (tid == 0) {
                 if (r >= 0) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the job's state and lattice
@@ -346,7 +349,7 @@ struct okpz_batch {
     JobState *d_state = nullptr;
     Control *d_ctl = nullptr;
     uint64_t *d_claim = nullptr;
-    int32_t *d_ngr = nullptr;
+    int32_t *d_sched = nullptr;
     int threads = 1024;
     int workgroups = 0;  // 0: two per compute unit
     int cus = 0;
@@ -415,7 +418,9 @@ int reset(okpz_batch *b, const std::vector<int32_t> &tmax)
     std::memset(st.data(), 0, st.size() * sizeof(JobState));
     std::vector<JobDesc> desc = b->desc;
     std::vector<uint64_t> claim(n);
-    std::vector<int32_t> ngr(n);
+    // items per sweep of each job, then the scan order: most remaining work
+    // first, so the longest dependency chains never wait behind short ones
+    std::vector<int32_t> sched(2 * (size_t)n);
     int finished = 0;
     for (int r = 0; r < n; ++r) {
         desc[r].t_max = tmax[r];
@@ -423,7 +428,7 @@ int reset(okpz_batch *b, const std::vector<int32_t> &tmax)
         int ns = 0;
         while (ns < (int)b->times[r].size() && b->times[r][ns] <= tmax[r]) ++ns;
         desc[r].nsamp = ns;
-        ngr[r] = desc[r].nitems;
+        sched[r] = desc[r].nitems;
         if (desc[r].t_max == 0) {
             claim[r] = okpz::batch::kClosed;
             ++finished;
@@ -431,12 +436,17 @@ int reset(okpz_batch *b, const std::vector<int32_t> &tmax)
             claim[r] = 0;  // sweep 0, group 0
         }
     }
+    std::vector<int32_t> order(n);
+    for (int r = 0; r < n; ++r) order[r] = r;
+    auto work = [&](int r) { return (int64_t)desc[r].Lx * desc[r].Ly * desc[r].t_max; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    std::copy(order.begin(), order.end(), sched.begin() + n);
     Control ctl{};
     ctl.finished = finished;
     BHIP(hipMemcpyAsync(b->d_desc, desc.data(), n * sizeof(JobDesc), hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_state, st.data(), n * sizeof(JobState), hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_claim, claim.data(), n * 8, hipMemcpyHostToDevice, b->stream));
-    BHIP(hipMemcpyAsync(b->d_ngr, ngr.data(), n * 4, hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(b->d_sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, b->stream));
     int maxwords = 0;
     for (auto &d : desc) maxwords = std::max(maxwords, 2 * d.Ly * d.W);
@@ -453,7 +463,7 @@ struct Ring {
     JobState *state;
     Control *ctl;
     uint64_t *claim;
-    int32_t *ngr;
+    int32_t *sched;  // items per sweep, then scan order
     int njobs;
     hipStream_t stream;
 };
@@ -473,7 +483,7 @@ hipError_t launch_ring(const Ring &R, int wgs)
     // the claim words plus a sleep of 16 x 64 cycles)
     const uint64_t idle_limit = 1ull << 19;
     hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads>), dim3(wgs), dim3(kThreads),
-                       okpz::core::kGroupLds, R.stream, R.desc, R.state, R.ctl, R.claim, R.ngr,
+                       okpz::core::kGroupLds, R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
                        (int32_t)R.njobs, idle_limit);
     return hipGetLastError();
 }
@@ -502,7 +512,7 @@ int check_control(const Ring &R)
 
 Ring ring_of(okpz_batch *b)
 {
-    return Ring{b->d_desc, b->d_state, b->d_ctl, b->d_claim, b->d_ngr, (int)b->jobs.size(), b->stream};
+    return Ring{b->d_desc, b->d_state, b->d_ctl, b->d_claim, b->d_sched, (int)b->jobs.size(), b->stream};
 }
 
 int run(okpz_batch *b, int threads, int wgs, float *ms)
@@ -589,7 +599,7 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
     }
     (void)groups;
     const size_t qoff = total;
-    total += al((size_t)n_jobs * 8) + al((size_t)n_jobs * 4);
+    total += al((size_t)n_jobs * 8) + al((size_t)n_jobs * 8);
     hipError_t e = hipMalloc(&b->mem, total);
     if (e != hipSuccess) {
         delete b;
@@ -601,7 +611,7 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
     b->d_ctl = reinterpret_cast<Control *>(base + al(n_jobs * sizeof(JobDesc)) +
                                            al(n_jobs * sizeof(JobState)));
     b->d_claim = reinterpret_cast<uint64_t *>(base + qoff);
-    b->d_ngr = reinterpret_cast<int32_t *>(base + qoff + al((size_t)n_jobs * 8));
+    b->d_sched = reinterpret_cast<int32_t *>(base + qoff + al((size_t)n_jobs * 8));
     for (int r = 0; r < n_jobs; ++r) {
         const okpz_job &j = jobs[r];
         JobDesc &d = b->desc[r];
@@ -885,7 +895,7 @@ struct okpz_server {
     JobState *d_state = nullptr;
     Control *d_ctl = nullptr;
     uint64_t *d_claim = nullptr;
-    int32_t *d_ngr = nullptr;
+    int32_t *d_sched = nullptr;
     hipStream_t stream = nullptr;
     int threads = 1024, wgs = 0, cus = 0;
     std::chrono::steady_clock::time_point t0;
@@ -1009,7 +1019,7 @@ int okpz_serve_create(okpz_server **out, size_t hbm_budget, int32_t max_slots,
     sv->m = m;
     sv->slot_job.assign(max_slots, -1);
     const size_t total = al(max_slots * sizeof(JobDesc)) + al(max_slots * sizeof(JobState)) +
-                         al(sizeof(Control)) + al((size_t)max_slots * 8) + al((size_t)max_slots * 4);
+                         al(sizeof(Control)) + al((size_t)max_slots * 8) + al((size_t)max_slots * 8);
     hipError_t e = hipMalloc(&sv->mem, total);
     if (e != hipSuccess) {
         delete sv;
@@ -1023,7 +1033,7 @@ int okpz_serve_create(okpz_server **out, size_t hbm_budget, int32_t max_slots,
     sv->d_ctl = reinterpret_cast<Control *>(base);
     base += al(sizeof(Control));
     sv->d_claim = reinterpret_cast<uint64_t *>(base);
-    sv->d_ngr = reinterpret_cast<int32_t *>(base + al((size_t)max_slots * 8));
+    sv->d_sched = reinterpret_cast<int32_t *>(base + al((size_t)max_slots * 8));
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1111,7 +1121,8 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
     // 2. quantum: every resident job advances by its share
     std::vector<JobDesc> desc(sv->max_slots);
     std::vector<uint64_t> claim(sv->max_slots, okpz::batch::kClosed);
-    std::vector<int32_t> ngr(sv->max_slots, 0);
+    // items per sweep of each slot, then the scan order: oldest job first
+    std::vector<int32_t> sched(2 * (size_t)sv->max_slots, 0);
     int active = 0, finished = 0;
     for (int i = 0; i < sv->max_slots; ++i) {
         std::memset(&desc[i], 0, sizeof(JobDesc));
@@ -1128,8 +1139,18 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
         desc[i] = J.desc;
         desc[i].t_max = (int32_t)stop;
         claim[i] = (uint64_t)J.s << 32;
-        ngr[i] = J.desc.nitems;
+        sched[i] = J.desc.nitems;
         ++active;
+    }
+    {
+        std::vector<int32_t> order(sv->max_slots);
+        for (int i = 0; i < sv->max_slots; ++i) order[i] = i;
+        auto arrival = [&](int i) {
+            return sv->slot_job[i] < 0 ? 1e300 : sv->jobs[sv->slot_job[i]].arrival;
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return arrival(x) < arrival(y); });
+        std::copy(order.begin(), order.end(), sched.begin() + sv->max_slots);
     }
     if (running) *running = active;
     if (waiting) *waiting = (int32_t)sv->waiting.size();
@@ -1139,13 +1160,13 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
     BHIP(hipMemcpyAsync(sv->d_desc, desc.data(), desc.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
                         sv->stream));
     BHIP(hipMemcpyAsync(sv->d_claim, claim.data(), claim.size() * 8, hipMemcpyHostToDevice, sv->stream));
-    BHIP(hipMemcpyAsync(sv->d_ngr, ngr.data(), ngr.size() * 4, hipMemcpyHostToDevice, sv->stream));
+    BHIP(hipMemcpyAsync(sv->d_sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice, sv->stream));
     BHIP(hipMemcpyAsync(sv->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, sv->stream));
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     BHIP(hipEventRecord(e0, sv->stream));
-    const Ring R{sv->d_desc, sv->d_state, sv->d_ctl, sv->d_claim, sv->d_ngr, sv->max_slots,
+    const Ring R{sv->d_desc, sv->d_state, sv->d_ctl, sv->d_claim, sv->d_sched, sv->max_slots,
                  sv->stream};
     hipError_t e = launch_any(R, sv->threads, sv->wgs ? sv->wgs : 2 * sv->cus);
     if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "serve launch: %s", hipGetErrorString(e));
