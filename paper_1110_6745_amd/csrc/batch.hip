@@ -280,10 +280,7 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
             __syncthreads();
             for (int y = wave; y < jd.Ly; y += nwave) core::width_row(v, y, lane, lut, jd.rows);
             __syncthreads();  // rows are read back by other waves of this workgroup (same CU)
-            int32_t *scan = reinterpret_cast<int32_t *>(smem);
-            int64_t *r1 = reinterpret_cast<int64_t *>(smem + 4 * 1024);
-            int64_t *r2 = reinterpret_cast<int64_t *>(smem + 12 * 1024);
-            core::width_combine(jd.rows, jd.Lx, jd.Ly, s_out, scan, r1, r2);
+            core::width_combine(jd.rows, jd.Lx, jd.Ly, s_out, reinterpret_cast<int64_t *>(smem));
             if (tid == 0) {
                 int64_t *o = jd.samples + 6 * (size_t)ns.next_sample;
                 o[0] = ns.s;

@@ -22,9 +22,8 @@ __global__ __launch_bounds__(kRowThreads) void width_rows_kernel(LatticeView v, 
 __global__ __launch_bounds__(kFinalThreads) void width_final_kernel(const int64_t *rows, int32_t Lx,
                                                                    int32_t Ly, int64_t *out)
 {
-    __shared__ int32_t scan[kFinalThreads];
-    __shared__ int64_t r1[kFinalThreads], r2[kFinalThreads];
-    core::width_combine(rows, Lx, Ly, out, scan, r1, r2);
+    __shared__ int64_t lds[64];
+    core::width_combine(rows, Lx, Ly, out, lds);
 }
 
 }  // namespace

@@ -112,48 +112,72 @@ __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
 }
 
 // Combine the rows into out[0..3] = {S1' lo, S1' hi, S2' lo, S2' hi} (128-bit
-// two's complement halves) with one workgroup of nthreads <= 1024 threads.
-// scan/r1/r2: LDS scratch of nthreads entries each.  Ends with a barrier.
+// two's complement halves) with one workgroup of up to 1024 threads.  Each
+// thread takes a run of rows; the column-0 prefix G(y) comes from a
+// wavefront scan plus the totals of the lower waves; sums of squares are
+// accumulated in 128 bits and reduced wave by wave.  lds: 64 entries of LDS
+// scratch.  Ends with a barrier.
 __device__ __forceinline__ void width_combine(const int64_t *rows, int32_t Lx, int32_t Ly,
-                                              int64_t *out, int32_t *scan, int64_t *r1,
-                                              int64_t *r2)
+                                              int64_t *out, int64_t *lds)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
     const int per = (Ly + nth - 1) / nth;
     const int ya = min(Ly, tid * per), yb = min(Ly, ya + per);
     const int64_t *rs1 = rows, *rs2 = rows + Ly, *col = rows + 2 * (size_t)Ly;
 
     int32_t local = 0;
     for (int y = ya; y < yb; ++y) local += 2 * (int32_t)col[y] - 1;
-    scan[tid] = local;
-    __syncthreads();
-    for (int o = 1; o < nth; o <<= 1) {
-        const int32_t t = tid >= o ? scan[tid - o] : 0;
-        __syncthreads();
-        scan[tid] += t;
-        __syncthreads();
+    int32_t incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
     }
-    int64_t G = scan[tid] - local;  // sum of sigma_y(0,k) for k < ya
-    int64_t s1 = 0, s2 = 0;
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    int64_t G = incl - local;  // sum of sigma_y(0,k) for k < ya
+    for (int w = 0; w < wave; ++w) G += lds[w];
+
+    int64_t s1 = 0;
+    __int128 s2 = 0;
     for (int y = ya; y < yb; ++y) {
         const int64_t p1 = rs1[y], p2 = rs2[y];
         s1 += (int64_t)Lx * G + p1;
-        s2 += (int64_t)Lx * G * G + 2 * G * p1 + p2;
+        s2 += (__int128)((int64_t)Lx * G * G + 2 * G * p1 + p2);
         G += 2 * col[y] - 1;
     }
-    r1[tid] = s1;
-    r2[tid] = s2;
+    uint64_t lo = (uint64_t)s2;
+    uint64_t hi = (uint64_t)(s2 >> 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t a1 = __shfl_down(s1, o, 64);
+        const uint64_t alo = __shfl_down(lo, o, 64);
+        const uint64_t ahi = __shfl_down(hi, o, 64);
+        s1 += a1;
+        const unsigned __int128 v = (((unsigned __int128)hi << 64) | lo) +
+                                    (((unsigned __int128)ahi << 64) | alo);
+        lo = (uint64_t)v;
+        hi = (uint64_t)(v >> 64);
+    }
+    __syncthreads();  // the scan totals are read above; lds is reused
+    if (lane == 0) {
+        lds[16 + wave] = s1;
+        lds[32 + wave] = (int64_t)lo;
+        lds[48 + wave] = (int64_t)hi;
+    }
     __syncthreads();
     if (tid == 0) {
-        __int128 t1 = 0, t2 = 0;
-        for (int i = 0; i < nth; ++i) {
-            t1 += r1[i];
-            t2 += r2[i];
+        __int128 t1 = 0;
+        unsigned __int128 t2 = 0;
+        for (int w = 0; w < nwave; ++w) {
+            t1 += lds[16 + w];
+            t2 += ((unsigned __int128)(uint64_t)lds[48 + w] << 64) | (uint64_t)lds[32 + w];
         }
         out[0] = (int64_t)(uint64_t)t1;
         out[1] = (int64_t)(t1 >> 64);
         out[2] = (int64_t)(uint64_t)t2;
-        out[3] = (int64_t)(t2 >> 64);
+        out[3] = (int64_t)(uint64_t)(t2 >> 64);
     }
     __syncthreads();
 }

@@ -106,3 +106,24 @@ def test_autotune_then_run(okpz):
     b.run()
     check_batch(okpz, b, jobs, M, refs)
     b.free()
+
+
+def test_single_large_job_equals_alone(okpz):
+    # one lattice alone in a persistent launch: every sweep's 64 groups are
+    # spread over the resident workgroups and handed over across XCDs
+    jobs = [(2048, 2048, 0.95, 0.05, 41, 25)]
+    refs = [alone(okpz, j, 0.2) for j in jobs]
+    b = okpz.Batch(jobs, 0.2)
+    b.run()
+    check_batch(okpz, b, jobs, 0.2, refs)
+    b.free()
+
+
+def test_large_and_small_lattices_in_one_launch(okpz):
+    jobs = [(4096, 4096, 1.0, 0.0, 31, 6), (2048, 2048, 0.95, 0.05, 32, 8),
+            (8192, 256, 1.0, 0.0, 33, 5), (64, 64, 1.0, 0.0, 34, 40), (32, 96, 0.5, 0.5, 35, 30)]
+    refs = [alone(okpz, j, 0.5) for j in jobs]
+    b = okpz.Batch(jobs, 0.5)
+    b.run()
+    check_batch(okpz, b, jobs, 0.5, refs)
+    b.free()
