@@ -73,6 +73,22 @@ __device__ __forceinline__ Ctr4 philox10_dev(Ctr4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
+// Rounds [r0, r1) of Philox4x32-10 on state c (the key of round i is
+// (k0 + i W0, k1 + i W1)); rounds 0..9 in order give philox10_dev.
+template <int r0, int r1>
+__device__ __forceinline__ void philox_rounds(Ctr4 &c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = r0; i < r1; ++i) {
+        const uint32_t ka = k0 + (uint32_t)i * 0x9E3779B9u, kb = k1 + (uint32_t)i * 0xBB67AE85u;
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t n0 = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), c.y, ka, 0x96);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), c.w, kb, 0x96);
+        c = Ctr4{n0, (uint32_t)m1, n2, (uint32_t)m0};
+    }
+}
+
 // 4 bits -> 4 bytes (bit j to bit 0 of byte j): nib * (1 + 2^7 + 2^14 + 2^21)
 // puts bit j at positions j + 7i, all distinct (no carries); byte j keeps
 // i = j.
@@ -239,14 +255,20 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     const uint32_t fixed_tbl = (a.Tp != 0 ? (1u << 24) : 0u) | (a.Tq != 0 ? (1u << 3) : 0u);
     (void)fixed_tbl;
 
-    for (int gs = 0; gs < kSteps / 8; ++gs) {
-        uint32_t sw[kCpt][4];
+    // Site words of 8 steps come from one Philox call per cell; the call for
+    // the next 8 steps is spread over the current ones (about 1.25 rounds
+    // per step), where it fills the wait for each step's LDS reads.
+    uint32_t sw[kCpt][4];
 #pragma unroll
-        for (int j = 0; j < kCpt; ++j) {
-            const Ctr4 r = philox10_dev(Ctr4{a.s, bidj[j], ((uint32_t)gs << 16) | cid[j], kTagSite},
-                                        a.k0, a.k1);
-            sw[j][0] = r.x; sw[j][1] = r.y; sw[j][2] = r.z; sw[j][3] = r.w;
-        }
+    for (int j = 0; j < kCpt; ++j) {
+        const Ctr4 r = philox10_dev(Ctr4{a.s, bidj[j], cid[j], kTagSite}, a.k0, a.k1);
+        sw[j][0] = r.x; sw[j][1] = r.y; sw[j][2] = r.z; sw[j][3] = r.w;
+    }
+    for (int gs = 0; gs < kSteps / 8; ++gs) {
+        Ctr4 nxt[kCpt];
+#pragma unroll
+        for (int j = 0; j < kCpt; ++j)
+            nxt[j] = Ctr4{a.s, bidj[j], ((uint32_t)(gs + 1) << 16) | cid[j], kTagSite};
         uint32_t aw[kCpt][4];
         uint32_t opv[kCpt];
 #pragma unroll
@@ -294,9 +316,30 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                 sv[j] = smem[off[j] + Bx];
                 lv[j] = smem[off[j] + Bx - 1];
                 dv[j] = smem[off[j]];
+            }
+            // While the reads are in flight: this step's share of the next
+            // Philox call, pinned here so that it is not sunk to its use.
+            if (gs + 1 < kSteps / 8) {
+#pragma unroll
+                for (int j = 0; j < kCpt; ++j) {
+                    switch (e) {  // rounds 0,1 | 1,2 | 2,3 | 3,5 | 5,6 | 6,7 | 7,8 | 8,10
+                    case 0: philox_rounds<0, 1>(nxt[j], a.k0, a.k1); break;
+                    case 1: philox_rounds<1, 2>(nxt[j], a.k0, a.k1); break;
+                    case 2: philox_rounds<2, 3>(nxt[j], a.k0, a.k1); break;
+                    case 3: philox_rounds<3, 5>(nxt[j], a.k0, a.k1); break;
+                    case 4: philox_rounds<5, 6>(nxt[j], a.k0, a.k1); break;
+                    case 5: philox_rounds<6, 7>(nxt[j], a.k0, a.k1); break;
+                    case 6: philox_rounds<7, 8>(nxt[j], a.k0, a.k1); break;
+                    default: philox_rounds<8, 10>(nxt[j], a.k0, a.k1); break;
+                    }
+                    asm volatile("" : "+v"(nxt[j].x), "+v"(nxt[j].y), "+v"(nxt[j].z), "+v"(nxt[j].w));
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kCpt; ++j) {
                 // the loads zero-extend; keep the code generator from
                 // re-narrowing the bytes (it would add masking operations)
-                asm("" : "+v"(sv[j]), "+v"(lv[j]), "+v"(dv[j]));
+                asm volatile("" : "+v"(sv[j]), "+v"(lv[j]), "+v"(dv[j]));
             }
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
@@ -329,6 +372,10 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                 }
             }
             __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < kCpt; ++j) {
+            sw[j][0] = nxt[j].x; sw[j][1] = nxt[j].y; sw[j][2] = nxt[j].z; sw[j][3] = nxt[j].w;
         }
     }
 
