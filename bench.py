@@ -90,7 +90,7 @@ def batch_leg(scale, m=0.001):
     work = sum(L * L * t for L, _, _, _, _, t in jobs)
     b = okpz.Batch(jobs, m)
     t0 = time.perf_counter()
-    mapping = b.autotune(max(2, int(min(t for *_, t in jobs))))
+    mapping = b.autotune(max(2, int(max(t for *_, t in jobs)) // 20))
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     dev_ms = b.run()
@@ -107,6 +107,7 @@ def batch_leg(scale, m=0.001):
     hist_L = 1024
     t_from = jobs[31][5] // 2
     counts, under, over = b.w2_histogram(hist_L, hist_L, t_from, 0.0, 20.0, 40)
+    n_cum, _, kappa = b.w2_cumulants(hist_L, hist_L, t_from)
     b.free()
     t0 = time.perf_counter()
     for L, _, p, q, seed, t_max in jobs:
@@ -123,7 +124,8 @@ def batch_leg(scale, m=0.001):
             "batched_site_updates_per_s": work / batched_s,
             "mapping": {"threads": mapping[0], "workgroups": mapping[1], "autotune_s": tune_s},
             "w2_histogram_L1024": {"t_from": t_from, "lo": 0.0, "hi": 20.0,
-                                   "counts": counts.tolist(), "under": under, "over": over}}
+                                   "counts": counts.tolist(), "under": under, "over": over},
+            "w2_cumulants_L1024": {"t_from": t_from, "samples": n_cum, "kappa": kappa.tolist()}}
 
 
 def serve_leg(n_jobs=64, rate=50.0, seed=7):

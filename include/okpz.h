@@ -150,8 +150,10 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
 int okpz_batch_set_mapping(okpz_batch *b, int32_t threads, int32_t workgroups);
 int okpz_batch_get_mapping(okpz_batch *b, int32_t *threads, int32_t *workgroups);
 
-/* Pick the mapping by timing every candidate on a bounded trial (all jobs
- * capped at trial_mcs sweeps, results discarded); keeps the fastest. */
+/* Pick the mapping by timing every candidate on a scaled-down copy of the
+ * workload: the longest job runs trial_mcs sweeps and every other job the
+ * same fraction of its own t_max (at least one sweep); results are
+ * discarded and the jobs reset.  Keeps the fastest candidate. */
 int okpz_batch_autotune(okpz_batch *b, int64_t trial_mcs, int32_t *threads, int32_t *workgroups);
 
 /* Run every job from the flat state to its t_max in one persistent launch.
@@ -172,6 +174,22 @@ int okpz_batch_samples(okpz_batch *b, int32_t job, int64_t *t, int64_t *sum_h, i
  * The steady-state width distribution of Sec. IV comes from such samples. */
 int okpz_batch_w2_histogram(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, double lo,
                             double hi, int32_t nbins, int64_t *counts, int64_t *under, int64_t *over);
+
+/* Steady-state statistics of Sec. IV over the same samples as
+ * okpz_batch_w2_histogram (t >= t_from, every job of size Lx x Ly):
+ * *count samples; nu[0..3] = non-central moments <(W^2)^n>, n = 1..4;
+ * kappa[0..3] = cumulants kappa_1..kappa_4 from them (Eq. (cumulants)).
+ * W^2 from the exact integer sums, moments accumulated in extended precision.
+ * OKPZ_EINVAL if no sample qualifies. */
+int okpz_batch_w2_cumulants(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, int64_t *count,
+                            double *nu, double *kappa);
+
+/* Scaled width distribution Psi_L(x) = <W^2> P_L(W^2 / <W^2>) (Sec. IV) over
+ * the same samples: the density of x = W^2 / <W^2> on nbins equal bins of
+ * [0, x_hi), psi[i] = (samples in bin i) / (count * bin width); *count =
+ * samples used (those with x >= x_hi fall outside every bin). */
+int okpz_batch_psi(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, double x_hi,
+                   int32_t nbins, double *psi, int64_t *count);
 
 /* Final state of one job: canonical lattice (bytes >= Lx*Ly) and H0. */
 int okpz_batch_get_lattice(okpz_batch *b, int32_t job, uint8_t *host, size_t bytes);

@@ -688,9 +688,16 @@ int okpz_batch_autotune(okpz_batch *b, int64_t trial_mcs, int32_t *threads, int3
 {
     if (!b) return bfail(OKPZ_EINVAL, "null batch");
     if (trial_mcs <= 0) return bfail(OKPZ_EINVAL, "trial_mcs must be positive");
+    // a scaled-down copy of the workload: the same mix of short and long
+    // dependency chains, the longest job running trial_mcs sweeps
+    int64_t longest = 1;
+    for (const auto &j : b->jobs) longest = std::max<int64_t>(longest, j.t_max);
     std::vector<int32_t> tmax(b->jobs.size());
-    for (size_t r = 0; r < b->jobs.size(); ++r)
-        tmax[r] = (int32_t)std::min<int64_t>(b->jobs[r].t_max, trial_mcs);
+    for (size_t r = 0; r < b->jobs.size(); ++r) {
+        const int64_t t = b->jobs[r].t_max;
+        const int64_t scaled = (t * std::min<int64_t>(trial_mcs, longest) + longest - 1) / longest;
+        tmax[r] = (int32_t)(t == 0 ? 0 : std::max<int64_t>(1, std::min<int64_t>(t, scaled)));
+    }
     const int cand_t[3] = {1024, 512, 256};
     const int cand_w[2] = {2 * b->cus, b->cus};
     float best = 1e30f;
@@ -747,13 +754,15 @@ int okpz_batch_samples(okpz_batch *b, int32_t job, int64_t *t, int64_t *sum_h, i
     return OKPZ_OK;
 }
 
-int okpz_batch_w2_histogram(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, double lo,
-                            double hi, int32_t nbins, int64_t *counts, int64_t *under, int64_t *over)
+}  // extern "C"
+
+namespace {
+
+// W^2 = (N S2 - S1^2) / N^2 (Eq. (Wdef)) of every sample with t >= t_from of
+// every job of size Lx x Ly, from the exact integer numerator.
+int w2_values(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, std::vector<double> *out)
 {
-    if (!b || !counts) return bfail(OKPZ_EINVAL, "null argument");
-    if (nbins <= 0 || !(hi > lo)) return bfail(OKPZ_EINVAL, "need nbins > 0 and hi > lo");
-    for (int i = 0; i < nbins; ++i) counts[i] = 0;
-    int64_t u = 0, o = 0;
+    out->clear();
     for (int32_t r = 0; r < (int32_t)b->jobs.size(); ++r) {
         if (b->jobs[r].Lx != Lx || b->jobs[r].Ly != Ly) continue;
         int32_t n = 0;
@@ -765,17 +774,94 @@ int okpz_batch_w2_histogram(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_fro
         const __int128 N = (__int128)Lx * Ly;
         for (int i = 0; i < n; ++i) {
             if (t[i] < t_from) continue;
-            // W^2 = (N S2 - S1^2) / N^2 from the exact integer numerator
             const __int128 num = N * (__int128)s2[i] - (__int128)s1[i] * s1[i];
-            const double w2 = (double)num / ((double)N * (double)N);
-            const double f = (w2 - lo) / (hi - lo) * nbins;
-            if (f < 0) ++u;
-            else if (f >= nbins) ++o;
-            else ++counts[(int)f];
+            out->push_back((double)num / ((double)N * (double)N));
         }
+    }
+    return OKPZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int okpz_batch_w2_histogram(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, double lo,
+                            double hi, int32_t nbins, int64_t *counts, int64_t *under, int64_t *over)
+{
+    if (!b || !counts) return bfail(OKPZ_EINVAL, "null argument");
+    if (nbins <= 0 || !(hi > lo)) return bfail(OKPZ_EINVAL, "need nbins > 0 and hi > lo");
+    std::vector<double> w;
+    int rc = w2_values(b, Lx, Ly, t_from, &w);
+    if (rc != OKPZ_OK) return rc;
+    for (int i = 0; i < nbins; ++i) counts[i] = 0;
+    int64_t u = 0, o = 0;
+    for (double w2 : w) {
+        const double f = (w2 - lo) / (hi - lo) * nbins;
+        if (f < 0) ++u;
+        else if (f >= nbins) ++o;
+        else ++counts[(int)f];
     }
     if (under) *under = u;
     if (over) *over = o;
+    return OKPZ_OK;
+}
+
+int okpz_batch_w2_cumulants(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, int64_t *count,
+                            double *nu, double *kappa)
+{
+    if (!b || !count || !nu || !kappa) return bfail(OKPZ_EINVAL, "null argument");
+    std::vector<double> w;
+    int rc = w2_values(b, Lx, Ly, t_from, &w);
+    if (rc != OKPZ_OK) return rc;
+    *count = (int64_t)w.size();
+    if (w.empty()) return bfail(OKPZ_EINVAL, "no samples of size %lldx%lld at t >= %lld",
+                                (long long)Lx, (long long)Ly, (long long)t_from);
+    long double m[5] = {0, 0, 0, 0, 0};
+    for (double v : w) {
+        const long double x = v;
+        m[1] += x;
+        m[2] += x * x;
+        m[3] += x * x * x;
+        m[4] += x * x * x * x;
+    }
+    for (int n = 1; n <= 4; ++n) m[n] /= (long double)w.size();
+    // cumulants from the non-central moments (Sec. IV, Eq. (cumulants))
+    const long double k1 = m[1];
+    const long double k2 = m[2] - m[1] * m[1];
+    const long double k3 = m[3] - 3 * m[1] * m[2] + 2 * m[1] * m[1] * m[1];
+    const long double k4 = m[4] - 4 * m[3] * m[1] - 3 * m[2] * m[2] + 12 * m[1] * m[1] * m[2] -
+                           6 * m[1] * m[1] * m[1] * m[1];
+    for (int n = 0; n < 4; ++n) nu[n] = (double)m[n + 1];
+    kappa[0] = (double)k1;
+    kappa[1] = (double)k2;
+    kappa[2] = (double)k3;
+    kappa[3] = (double)k4;
+    return OKPZ_OK;
+}
+
+int okpz_batch_psi(okpz_batch *b, int64_t Lx, int64_t Ly, int64_t t_from, double x_hi,
+                   int32_t nbins, double *psi, int64_t *count)
+{
+    if (!b || !psi || !count) return bfail(OKPZ_EINVAL, "null argument");
+    if (nbins <= 0 || !(x_hi > 0)) return bfail(OKPZ_EINVAL, "need nbins > 0 and x_hi > 0");
+    std::vector<double> w;
+    int rc = w2_values(b, Lx, Ly, t_from, &w);
+    if (rc != OKPZ_OK) return rc;
+    *count = (int64_t)w.size();
+    if (w.empty()) return bfail(OKPZ_EINVAL, "no samples of size %lldx%lld at t >= %lld",
+                                (long long)Lx, (long long)Ly, (long long)t_from);
+    long double mean = 0;
+    for (double v : w) mean += v;
+    mean /= (long double)w.size();
+    if (!(mean > 0)) return bfail(OKPZ_EINVAL, "mean W^2 is not positive");
+    for (int i = 0; i < nbins; ++i) psi[i] = 0;
+    const double dx = x_hi / nbins;
+    for (double v : w) {
+        const double f = (double)((long double)v / mean) / dx;
+        if (f >= 0 && f < nbins) psi[(int)f] += 1.0;
+    }
+    // density of x = W^2 / <W^2>: Psi_L(x) = <W^2> P_L(W^2) (Sec. IV)
+    for (int i = 0; i < nbins; ++i) psi[i] /= (double)w.size() * dx;
     return OKPZ_OK;
 }
 

@@ -94,6 +94,10 @@ _sig("okpz_batch_get_lattice", ctypes.c_int, _vp, ctypes.c_int32, _u8p, _sz)
 _sig("okpz_batch_h0", ctypes.c_int, _vp, ctypes.c_int32, _i64p)
 _sig("okpz_batch_w2_histogram", ctypes.c_int, _vp, _i64, _i64, _i64, ctypes.c_double,
      ctypes.c_double, ctypes.c_int32, _i64p, _i64p, _i64p)
+_dp = ctypes.POINTER(ctypes.c_double)
+_sig("okpz_batch_w2_cumulants", ctypes.c_int, _vp, _i64, _i64, _i64, _i64p, _dp, _dp)
+_sig("okpz_batch_psi", ctypes.c_int, _vp, _i64, _i64, _i64, ctypes.c_double, ctypes.c_int32, _dp,
+     _i64p)
 _sig("okpz_batch_free", ctypes.c_int, _vp)
 _sig("okpz_batch_last_error", ctypes.c_char_p)
 
@@ -117,7 +121,8 @@ EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_free", "okpz_last_error", "okpz_batch_create", "okpz_batch_set_mapping",
             "okpz_batch_get_mapping", "okpz_batch_autotune", "okpz_batch_run",
             "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
-            "okpz_batch_w2_histogram", "okpz_serve_create", "okpz_serve_set_mapping",
+            "okpz_batch_w2_histogram", "okpz_batch_w2_cumulants", "okpz_batch_psi",
+            "okpz_serve_create", "okpz_serve_set_mapping",
             "okpz_serve_now", "okpz_serve_submit", "okpz_serve_step", "okpz_serve_job",
             "okpz_serve_samples", "okpz_serve_result", "okpz_serve_stats", "okpz_serve_free",
             "okpz_batch_free", "okpz_batch_last_error"]
@@ -285,6 +290,8 @@ class Batch:
         return t.value, w.value
 
     def autotune(self, trial_mcs: int) -> tuple:
+        """Time each (threads, workgroups) candidate on the workload scaled so
+        that the longest job runs trial_mcs sweeps; keep and return the best."""
         t, w = ctypes.c_int32(), ctypes.c_int32()
         _bcheck(_lib.okpz_batch_autotune(self._h, int(trial_mcs), ctypes.byref(t),
                                          ctypes.byref(w)))
@@ -327,6 +334,24 @@ class Batch:
                                              counts.ctypes.data_as(_i64p), ctypes.byref(u),
                                              ctypes.byref(o)))
         return counts, u.value, o.value
+
+    def w2_cumulants(self, Lx: int, Ly: int, t_from: int):
+        """(count, nu[4], kappa[4]): moments and cumulants of W^2 over the
+        samples with t >= t_from of size Lx x Ly (okpz_batch_w2_cumulants)."""
+        n = ctypes.c_int64()
+        nu = np.zeros(4)
+        kappa = np.zeros(4)
+        _bcheck(_lib.okpz_batch_w2_cumulants(self._h, Lx, Ly, t_from, ctypes.byref(n),
+                                             nu.ctypes.data_as(_dp), kappa.ctypes.data_as(_dp)))
+        return n.value, nu, kappa
+
+    def psi(self, Lx: int, Ly: int, t_from: int, x_hi: float, nbins: int):
+        """(psi[nbins], count): density of W^2 / <W^2> on [0, x_hi) (okpz_batch_psi)."""
+        out = np.zeros(nbins)
+        n = ctypes.c_int64()
+        _bcheck(_lib.okpz_batch_psi(self._h, Lx, Ly, t_from, float(x_hi), nbins,
+                                    out.ctypes.data_as(_dp), ctypes.byref(n)))
+        return out, n.value
 
     def free(self) -> None:
         if self._h:

@@ -127,3 +127,51 @@ def test_large_and_small_lattices_in_one_launch(okpz):
     b.run()
     check_batch(okpz, b, jobs, 0.5, refs)
     b.free()
+
+
+def paper_sampling_times(t_max, m):
+    """ceil of t_(i+1) = (t_i + 10) e^m from t_0 = 0 (Sec. III), then t_max."""
+    import math
+
+    out, t = [], 0.0
+    while True:
+        t = (t + 10.0) * math.exp(m)
+        if t > t_max:
+            break
+        out.append(math.ceil(t))
+    out = sorted(set(out))
+    if t_max > 0 and (not out or out[-1] != t_max):
+        out.append(t_max)
+    return out
+
+
+def test_steady_state_statistics_match_oracle(okpz):
+    # cumulants (Eq. (cumulants)) and Psi_L of the batch's samples against
+    # the oracle's exact statistics of its own runs of the same realizations
+    from oracle import stats
+
+    m, t_max, t_from, R = 0.05, 120, 40, 6
+    groups = [(32, 1.0, 0.0, 100), (64, 0.95, 0.05, 200)]
+    jobs = [(L, L, p, q, s0 + r, t_max) for (L, p, q, s0) in groups for r in range(R)]
+    b = okpz.Batch(jobs, m)
+    b.run()
+    times = [t for t in paper_sampling_times(t_max, m) if t >= t_from]
+    for L, p, q, s0 in groups:
+        ens = oracle.ensemble(L, L, p, q, s0, R, t_max)  # S1, S2 after MCS 1..t_max
+        vals = [stats.w2_exact(int(ens[r, t - 1, 0]), int(ens[r, t - 1, 1]), L * L)
+                for r in range(R) for t in times]
+        nu_x = [float(v) for v in stats.moments(vals)]
+        k_x = [float(v) for v in stats.cumulants(vals)]
+        n, nu, kappa = b.w2_cumulants(L, L, t_from)
+        assert n == len(vals)
+        for i in range(4):
+            assert nu[i] == pytest.approx(nu_x[i], rel=1e-12)
+            scale = abs(k_x[1]) ** ((i + 1) / 2)
+            assert abs(kappa[i] - k_x[i]) <= 1e-9 * (abs(k_x[i]) + scale)
+        x_hi, nb = 3.0, 24
+        ps, cnt = b.psi(L, L, t_from, x_hi, nb)
+        ps_x = stats.psi(vals, x_hi, nb)
+        assert cnt == len(vals)
+        # at most one sample on a bin edge may fall on the other side
+        assert np.abs(ps - np.array(ps_x)).sum() <= 2.0 / (cnt * x_hi / nb) + 1e-12
+    b.free()
