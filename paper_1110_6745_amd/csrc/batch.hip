@@ -182,7 +182,7 @@ __device__ int find_and_claim(uint64_t *claim, const int32_t *nitems, const int3
 }
 
 template <int kThreads>
-__global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, JobState *state,
+__global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const JobDesc *jobs, JobState *state,
                                                          Control *ctl, uint64_t *claim,
                                                          const int32_t *sched, int32_t njobs,
                                                          uint64_t idle_limit)
@@ -228,8 +228,10 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const JobDesc *jobs, Jo
             }
         }
         __syncthreads();
-        const int r = s_job;
-        const uint64_t w = s_claim;
+        // uniform across the workgroup: readfirstlane lets the job's
+        // descriptor and state be fetched with scalar loads into SGPRs
+        const int r = __builtin_amdgcn_readfirstlane(s_job);
+        const uint64_t w = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)s_claim);
         __syncthreads();
         if (r == -1) break;
         if (r == -2) continue;
@@ -347,7 +349,7 @@ struct okpz_batch {
     Control *d_ctl = nullptr;
     uint64_t *d_claim = nullptr;
     int32_t *d_sched = nullptr;
-    int threads = 1024;
+    int threads = 512;  // two workgroups per CU without spills
     int workgroups = 0;  // 0: two per compute unit
     int cus = 0;
     hipStream_t stream = nullptr;
@@ -980,7 +982,7 @@ struct okpz_server {
     uint64_t *d_claim = nullptr;
     int32_t *d_sched = nullptr;
     hipStream_t stream = nullptr;
-    int threads = 1024, wgs = 0, cus = 0;
+    int threads = 512, wgs = 0, cus = 0;  // two workgroups per CU without spills
     std::chrono::steady_clock::time_point t0;
     int64_t quanta = 0, done = 0;
     double device_ms = 0;

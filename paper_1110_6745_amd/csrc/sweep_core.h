@@ -139,7 +139,11 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         a.Bx = kFixedB;
         a.By = kFixedB;
     }
-    const int tid = threadIdx.x;
+    // opaque copy of the thread index: in the persistent batch kernel this
+    // keeps the compiler from hoisting thread-constant values (counters,
+    // cell offsets) out of the work loop, which would pin them in registers
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int Bx = a.Bx, By = a.By;
     const int wpr = Bx >> 5;
     const int tsz = (By + 1) * Bx;  // bytes per tile incl. guard row
