@@ -287,7 +287,9 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                     aw[j][0] = r.x; aw[j][1] = r.y; aw[j][2] = r.z; aw[j][3] = r.w;
                 }
             }
-            // all reads of the step first: the cells' byte sets are disjoint
+            // all reads of the step first: the cells' byte sets are disjoint.
+            // For a site byte that is neither 0 nor 0x1B the neighbour bytes
+            // stay 0, which no test below can turn into a move.
             uint32_t off[kCpt], sv[kCpt], lv[kCpt], dv[kCpt];
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
@@ -318,8 +320,6 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                     off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
                 }
                 sv[j] = smem[off[j] + Bx];
-                lv[j] = smem[off[j] + Bx - 1];
-                dv[j] = smem[off[j]];
             }
             // While the reads are in flight: this step's share of the next
             // Philox call, pinned here so that it is not sunk to its use.
@@ -343,7 +343,18 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             for (int j = 0; j < kCpt; ++j) {
                 // the loads zero-extend; keep the code generator from
                 // re-narrowing the bytes (it would add masking operations)
-                asm volatile("" : "+v"(sv[j]), "+v"(lv[j]), "+v"(dv[j]));
+                asm volatile("" : "+v"(sv[j]));
+                // Only a site at a local minimum (byte 0) or maximum (0x1B)
+                // can move; only those lanes read the two neighbour bytes,
+                // which roughly halves the LDS read traffic of a step.
+                lv[j] = 0;
+                dv[j] = 0;
+                const bool cand = (sv[j] == 0u) || (kMode != kGrowth && sv[j] == 0x1Bu);
+                if (cand) {
+                    lv[j] = smem[off[j] + Bx - 1];
+                    dv[j] = smem[off[j]];
+                }
+                asm volatile("" : "+v"(lv[j]), "+v"(dv[j]));
             }
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
