@@ -268,6 +268,11 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         const Ctr4 r = philox10_dev(Ctr4{a.s, bidj[j], cid[j], kTagSite}, a.k0, a.k1);
         sw[j][0] = r.x; sw[j][1] = r.y; sw[j][2] = r.z; sw[j][3] = r.w;
     }
+    // neighbour bytes: a lane whose site cannot move keeps the bytes it read
+    // last (any value gives no move, see below), so no per-step reset is needed
+    uint32_t lv[kCpt], dv[kCpt];
+#pragma unroll
+    for (int j = 0; j < kCpt; ++j) lv[j] = dv[j] = 0;
     for (int gs = 0; gs < kSteps / 8; ++gs) {
         Ctr4 nxt[kCpt];
 #pragma unroll
@@ -288,9 +293,10 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                 }
             }
             // all reads of the step first: the cells' byte sets are disjoint.
-            // For a site byte that is neither 0 nor 0x1B the neighbour bytes
-            // stay 0, which no test below can turn into a move.
-            uint32_t off[kCpt], sv[kCpt], lv[kCpt], dv[kCpt];
+            // For a site byte that is neither 0 nor 0x1B the low three bits
+            // of the site byte already rule out a move, whatever the
+            // neighbour bytes hold.
+            uint32_t off[kCpt], sv[kCpt];
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
                 if ((e & 1) == 0) {
@@ -347,8 +353,6 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                 // Only a site at a local minimum (byte 0) or maximum (0x1B)
                 // can move; only those lanes read the two neighbour bytes,
                 // which roughly halves the LDS read traffic of a step.
-                lv[j] = 0;
-                dv[j] = 0;
                 const bool cand = (sv[j] == 0u) || (kMode != kGrowth && sv[j] == 0x1Bu);
                 if (cand) {
                     lv[j] = smem[off[j] + Bx - 1];
