@@ -301,6 +301,18 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
     }
 }
 
+// One width sample of a job run with plain sweep launches: t, the 128-bit
+// sums from out[0..3] and H0, in the layout the persistent kernel writes.
+__global__ void record_sample_kernel(int64_t *sample, int32_t t, const int64_t *out,
+                                     const int64_t *h0)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sample[0] = t;
+        for (int i = 0; i < 4; ++i) sample[1 + i] = out[i];
+        sample[5] = *h0;
+    }
+}
+
 // Flat zig-zag state h = (x+y) mod 2 in copy 0 of every job, H0 = 0.
 __global__ void init_jobs_kernel(const JobDesc *jobs, int32_t njobs)
 {
@@ -946,6 +958,10 @@ struct ServeJob {
     JobDesc desc{};
     std::vector<int32_t> times;
     int32_t s = 0;  // MCS completed (host mirror)
+    // large lattices run as plain per-lattice sweeps (see okpz_serve_step);
+    // their state lives on the host
+    bool grid = false;
+    int32_t ox = 0, cur = 0, next_sample = 0;
     std::vector<int64_t> raw;
     std::vector<uint8_t> lattice;
     int64_t h0 = 0;
@@ -954,7 +970,7 @@ struct ServeJob {
 size_t job_bytes(const okpz_job &j, size_t nsamp)
 {
     const size_t lat = al(2 * (size_t)j.Ly * (size_t)(j.Lx / 32) * 4);
-    return 2 * lat + al(8) + al(3 * (size_t)j.Ly * 8) + al(6 * 8 * std::max<size_t>(1, nsamp)) +
+    return 2 * lat + al(8) + al((3 * (size_t)j.Ly + 4) * 8) + al(6 * 8 * std::max<size_t>(1, nsamp)) +
            al(4 * std::max<size_t>(1, nsamp));
 }
 
@@ -965,6 +981,12 @@ size_t job_bytes(const okpz_job &j, size_t nsamp)
 // that fits one workgroup (staging, 64 barrier-separated steps, store and
 // the hand-over to the next sweep).
 constexpr double kNominalRate = 1.0e12;
+// Lattices with at least this many groups per sweep (4096 x 4096 and up)
+// run as plain per-lattice sweep launches on a second stream, next to the
+// persistent launch: one large sweep fills the device by itself, while
+// through the claim words its groups would be handed out one atomic at a
+// time.
+constexpr int kGridGroups = 256;
 constexpr double kSweepLatency = 2.0e-5;
 
 struct okpz_server {
@@ -982,6 +1004,7 @@ struct okpz_server {
     uint64_t *d_claim = nullptr;
     int32_t *d_sched = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t grid_stream = nullptr;  // plain sweeps of large lattices
     int threads = 512, wgs = 0, cus = 0;  // two workgroups per CU without spills
     std::chrono::steady_clock::time_point t0;
     int64_t quanta = 0, done = 0;
@@ -1005,6 +1028,10 @@ int retire(okpz_server *sv, ServeJob &J, double t)
     if (J.keep_lattice) {
         JobState st;
         BHIP(hipMemcpy(&st, sv->d_state + J.slot, sizeof st, hipMemcpyDeviceToHost));
+        if (J.grid) {
+            st.ox = J.ox;
+            st.cur = J.cur;
+        }
         std::vector<uint32_t> pl(2 * (size_t)d.Ly * d.W);
         BHIP(hipMemcpy(pl.data(), st.cur ? d.buf[1] : d.buf[0], pl.size() * 4, hipMemcpyDeviceToHost));
         J.lattice.resize((size_t)d.Lx * d.Ly);
@@ -1063,8 +1090,9 @@ int admit(okpz_server *sv, ServeJob &J, int slot, double t)
     d.buf[1] = reinterpret_cast<uint32_t *>(p + lat);
     d.h0 = reinterpret_cast<int64_t *>(p + 2 * lat);
     d.rows = reinterpret_cast<int64_t *>(p + 2 * lat + al(8));
-    d.samples = reinterpret_cast<int64_t *>(p + 2 * lat + al(8) + al(3 * (size_t)j.Ly * 8));
-    int32_t *tt = reinterpret_cast<int32_t *>(p + 2 * lat + al(8) + al(3 * (size_t)j.Ly * 8) +
+    const size_t rows_b = al((3 * (size_t)j.Ly + 4) * 8);
+    d.samples = reinterpret_cast<int64_t *>(p + 2 * lat + al(8) + rows_b);
+    int32_t *tt = reinterpret_cast<int32_t *>(p + 2 * lat + al(8) + rows_b +
                                                al(6 * 8 * std::max<size_t>(1, d.nsamp)));
     d.sample_t = tt;
     if (d.nsamp) BHIP(hipMemcpy(tt, J.times.data(), 4 * (size_t)d.nsamp, hipMemcpyHostToDevice));
@@ -1081,6 +1109,65 @@ int admit(okpz_server *sv, ServeJob &J, int slot, double t)
     J.state = 1;
     J.admit = t;
     J.s = 0;
+    J.grid = d.ngroups >= kGridGroups;
+    J.ox = 0;
+    J.cur = 0;
+    J.next_sample = 0;
+    return OKPZ_OK;
+}
+
+// Advance a large job to sweep `stop` with plain per-lattice sweep launches
+// (and width launches at its sampling times) on the server's second stream.
+int run_grid(okpz_server *sv, ServeJob &J, int64_t stop)
+{
+    const JobDesc &d = J.desc;
+    okpz::Geometry g;
+    okpz::geometry_of(d.Lx, d.Ly, &g);
+    okpz::SweepLaunch a{};
+    a.h0 = d.h0;
+    a.Lx = d.Lx;
+    a.Ly = d.Ly;
+    a.W = d.W;
+    a.Bx = d.Bx;
+    a.By = d.By;
+    a.nbx = d.nbx;
+    a.nby = d.nby;
+    a.k0 = d.k0;
+    a.k1 = d.k1;
+    a.Tp = d.Tp;
+    a.Tq = d.Tq;
+    a.need_accept_draws = d.mode == okpz::core::kDraw ? 1 : 0;
+    while (J.s < stop) {
+        const uint32_t sw = (uint32_t)J.s;
+        int32_t sx, sy;
+        okpz::block_shift(d.k0, d.k1, sw, g, &sx, &sy);
+        const int64_t x00 = (d.Lx - sx) % d.Lx, y00 = (d.Ly - sy) % d.Ly;
+        a.blk00 = (int32_t)((y00 / d.By) * d.nbx + x00 / d.Bx);
+        a.u00 = (int32_t)(x00 % d.Bx);
+        a.v00 = (int32_t)(y00 % d.By);
+        a.src = d.buf[J.cur];
+        a.dst = d.buf[J.cur ^ 1];
+        a.ox_src = J.ox;
+        a.sx = sx;
+        a.sy = sy;
+        a.s = sw;
+        hipError_t e = okpz::launch_sweep(a, 1024, sv->grid_stream);
+        if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "serve sweep: %s", hipGetErrorString(e));
+        J.cur ^= 1;
+        J.ox = sx;
+        J.s += 1;
+        if (J.next_sample < d.nsamp && J.times[J.next_sample] == J.s) {
+            const okpz::LatticeView v{d.buf[J.cur], d.Lx, d.Ly, d.W, J.ox};
+            int64_t *out = d.rows + 3 * (size_t)d.Ly;
+            e = okpz::launch_width(v, d.rows, out, sv->grid_stream);
+            if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "serve width: %s", hipGetErrorString(e));
+            hipLaunchKernelGGL(okpz::batch::record_sample_kernel, dim3(1), dim3(64), 0,
+                               sv->grid_stream, d.samples + 6 * (size_t)J.next_sample, J.s, out,
+                               d.h0);
+            BHIP(hipGetLastError());
+            ++J.next_sample;
+        }
+    }
     return OKPZ_OK;
 }
 
@@ -1124,7 +1211,9 @@ int okpz_serve_create(okpz_server **out, size_t hbm_budget, int32_t max_slots,
     (void)hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (sv->cus <= 0) sv->cus = 256;
     e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->grid_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        if (sv->stream) (void)hipStreamDestroy(sv->stream);
         (void)hipFree(sv->mem);
         delete sv;
         return bfail(OKPZ_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
@@ -1203,12 +1292,15 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
             if (rc != OKPZ_OK) return rc;
         }
     }
-    // 2. quantum: every resident job advances by its share
+    // 2. quantum: every resident job advances by its share; small jobs in one
+    // persistent launch, large ones (J.grid) as plain sweep launches on the
+    // second stream at the same time
     std::vector<JobDesc> desc(sv->max_slots);
     std::vector<uint64_t> claim(sv->max_slots, okpz::batch::kClosed);
     // items per sweep of each slot, then the scan order: oldest job first
     std::vector<int32_t> sched(2 * (size_t)sv->max_slots, 0);
-    int active = 0, finished = 0;
+    std::vector<std::pair<int64_t, int64_t>> grid_jobs;  // (job, stop)
+    int active = 0, finished = 0, n_small = 0;
     for (int i = 0; i < sv->max_slots; ++i) {
         std::memset(&desc[i], 0, sizeof(JobDesc));
         const int64_t k = sv->slot_job[i];
@@ -1221,11 +1313,17 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
         const double sweep_s = kSweepLatency + (double)(J.job.Lx * J.job.Ly) / kNominalRate;
         const int64_t share = std::max<int64_t>(1, (int64_t)(quantum_s / sweep_s));
         const int64_t stop = std::min<int64_t>(J.job.t_max, J.s + share);
+        ++active;
+        if (J.grid) {
+            grid_jobs.push_back({k, stop});
+            ++finished;  // not in the persistent launch
+            continue;
+        }
         desc[i] = J.desc;
         desc[i].t_max = (int32_t)stop;
         claim[i] = (uint64_t)J.s << 32;
         sched[i] = J.desc.nitems;
-        ++active;
+        ++n_small;
     }
     {
         std::vector<int32_t> order(sv->max_slots);
@@ -1240,30 +1338,47 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
     if (running) *running = active;
     if (waiting) *waiting = (int32_t)sv->waiting.size();
     if (active == 0) return OKPZ_OK;
-    Control ctl{};
-    ctl.finished = finished;
-    BHIP(hipMemcpyAsync(sv->d_desc, desc.data(), desc.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
-                        sv->stream));
-    BHIP(hipMemcpyAsync(sv->d_claim, claim.data(), claim.size() * 8, hipMemcpyHostToDevice, sv->stream));
-    BHIP(hipMemcpyAsync(sv->d_sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice, sv->stream));
-    BHIP(hipMemcpyAsync(sv->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, sv->stream));
-    hipEvent_t e0, e1;
+    hipEvent_t e0, e1, eg;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
+    BHIP(hipEventCreate(&eg));
     BHIP(hipEventRecord(e0, sv->stream));
     const Ring R{sv->d_desc, sv->d_state, sv->d_ctl, sv->d_claim, sv->d_sched, sv->max_slots,
                  sv->stream};
-    hipError_t e = launch_any(R, sv->threads, sv->wgs ? sv->wgs : 2 * sv->cus);
-    if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "serve launch: %s", hipGetErrorString(e));
+    if (n_small > 0) {
+        Control ctl{};
+        ctl.finished = finished;
+        BHIP(hipMemcpyAsync(sv->d_desc, desc.data(), desc.size() * sizeof(JobDesc),
+                            hipMemcpyHostToDevice, sv->stream));
+        BHIP(hipMemcpyAsync(sv->d_claim, claim.data(), claim.size() * 8, hipMemcpyHostToDevice,
+                            sv->stream));
+        BHIP(hipMemcpyAsync(sv->d_sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice,
+                            sv->stream));
+        BHIP(hipMemcpyAsync(sv->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, sv->stream));
+        // beside plain sweeps, one persistent workgroup per CU leaves room for them
+        const int wgs = sv->wgs ? sv->wgs : (grid_jobs.empty() ? 2 : 1) * sv->cus;
+        hipError_t e = launch_any(R, sv->threads, wgs);
+        if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "serve launch: %s", hipGetErrorString(e));
+    }
+    if (!grid_jobs.empty()) {
+        BHIP(hipStreamWaitEvent(sv->grid_stream, e0, 0));
+        for (const auto &gj : grid_jobs) {
+            const int rc = run_grid(sv, sv->jobs[gj.first], gj.second);
+            if (rc != OKPZ_OK) return rc;
+        }
+        BHIP(hipEventRecord(eg, sv->grid_stream));
+        BHIP(hipStreamWaitEvent(sv->stream, eg, 0));
+    }
     BHIP(hipEventRecord(e1, sv->stream));
     BHIP(hipStreamSynchronize(sv->stream));
     float ms = 0.f;
     BHIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(eg);
     sv->device_ms += ms;
     ++sv->quanta;
-    int rc = check_control(R);
+    int rc = n_small > 0 ? check_control(R) : OKPZ_OK;
     if (rc != OKPZ_OK) return rc;
     // 3. retire finished jobs
     std::vector<JobState> st(sv->max_slots);
@@ -1273,7 +1388,7 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
         const int64_t k = sv->slot_job[i];
         if (k < 0) continue;
         ServeJob &J = sv->jobs[k];
-        J.s = st[i].s;
+        if (!J.grid) J.s = st[i].s;  // grid jobs keep their state on the host
         if (J.s >= J.job.t_max) {
             rc = retire(sv, J, t);
             if (rc != OKPZ_OK) return rc;
@@ -1362,7 +1477,9 @@ int okpz_serve_free(okpz_server *sv)
     for (auto &J : sv->jobs)
         if (J.mem) (void)hipFree(J.mem);
     if (sv->mem) (void)hipFree(sv->mem);
+    if (sv->grid_stream) (void)hipStreamSynchronize(sv->grid_stream);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    if (sv->grid_stream) (void)hipStreamDestroy(sv->grid_stream);
     delete sv;
     return OKPZ_OK;
 }

@@ -44,6 +44,26 @@ def test_mix_equals_alone_with_staggered_arrivals(okpz):
     sv.free()
 
 
+def test_large_jobs_on_plain_sweeps_equal_alone(okpz):
+    # 4096^2 and 8192 x 2048 lattices (256 groups per sweep) run as plain
+    # sweep launches beside the persistent launch of the small jobs; the mix
+    # must still give every job's own trajectory
+    m = 0.3
+    jobs = [(4096, 4096, 1.0, 0.0, 51, 7), (64, 64, 0.95, 0.05, 52, 40),
+            (8192, 2048, 0.9, 0.2, 53, 5), (256, 256, 1.0, 0.0, 54, 25), (32, 32, 0.5, 0.5, 55, 50)]
+    sv = okpz.Server(hbm_budget=1 << 31, max_slots=4, quantum_sites=1 << 26, m=m)
+    ids = [sv.submit(j, arrival=0.001 * k, keep_lattice=True) for k, j in enumerate(jobs)]
+    sv.drain()
+    assert sv.stats()["done"] == len(jobs)
+    for i, job in zip(ids, jobs):
+        ref, lat, h0 = alone(okpz, job, m)
+        t, s1, s2 = sv.samples(i)
+        assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref, f"job {job}"
+        got, gh0 = sv.result(i, lattice=True)
+        assert np.array_equal(got, lat) and gh0 == h0, f"job {job}"
+    sv.free()
+
+
 def test_admission_respects_slots_and_bytes(okpz):
     # budget fits exactly two 512^2 jobs: never more than two are resident
     per = okpz.okpz_required_bytes(512, 512)
