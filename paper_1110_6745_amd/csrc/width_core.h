@@ -4,11 +4,11 @@
 //
 // h(x,y) = H0 + G(y) + P_y(x), with G(y) = sum_{k<y} sigma_y(0,k) and
 // P_y(x) = sum_{l<x} sigma_x(l,y).  width_row: one wavefront reads row y's
-// words once, re-aligned to physical columns with a funnel shift; each lane
-// takes four consecutive words, sums them chunk by chunk through a 256-entry
-// table of 8-site partial sums, a wavefront prefix scan of the segments'
-// height changes gives every segment's starting height, and the lane adds its
-// segment's exact sum and sum of squares.  width_combine: one workgroup
+// words once, in stored order with aligned 16-byte loads; each lane takes
+// four consecutive words, sums them chunk by chunk through a 256-entry table
+// of 8-site partial sums, a wavefront prefix scan of the segments' height
+// changes gives every segment's starting height, and the row's rotation is
+// undone in closed form at the end.  width_combine: one workgroup
 // scans the column-0 sigma_y bits to get G(y) and combines the rows into
 // 128-bit S1' = sum (h - H0) and S2' = sum (h - H0)^2.
 #pragma once
@@ -38,50 +38,62 @@ __device__ __forceinline__ void width_lut_build(uint32_t *lut)
     }
 }
 
-// Row y of lattice view v by one wavefront (lane = threadIdx.x & 63), four
-// consecutive words per lane per pass; lane 0 writes rows[y] = sum_x P,
-// rows[Ly + y] = sum_x P^2, rows[2 Ly + y] = the sigma_y bit at physical
-// column 0.  lut: the chunk table in LDS.
+// Row y of lattice view v by one wavefront (lane = threadIdx.x & 63); lane 0
+// writes rows[y] = sum_x P, rows[Ly + y] = sum_x P^2, rows[2 Ly + y] = the
+// sigma_y bit at physical column 0.  lut: the chunk table in LDS.
+//
+// The row is read in stored order, four aligned words per lane per pass.
+// With Q(c) the sigma_x prefix over stored columns c' < c and xs0 the stored
+// column of physical column 0, the full row sums to zero (a periodic row), so
+// P(x) = Q((xs0 + x) mod Lx) - Q(xs0) for every x; the physical sums follow
+// from the stored-order ones:
+//   sum P = sum Q - Lx Q(xs0),  sum P^2 = sum Q^2 - 2 Q(xs0) sum Q + Lx Q(xs0)^2.
 __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
                                          const uint32_t *lut, int64_t *rows)
 {
     constexpr int kWpl = 4;
     const uint32_t *row = v.planes + (size_t)y * v.W;
     const int xs0 = (v.Lx - v.ox) % v.Lx;  // stored column of physical column 0
-    const uint32_t off = (uint32_t)(xs0 & 31);
-    const int gws = xs0 >> 5;
+    const int wq = xs0 >> 5;
+    const uint32_t bq = (uint32_t)(xs0 & 31);
+    const bool vec = (v.W & 3) == 0;  // rows are 16-byte aligned
 
-    int64_t a1 = 0, a2 = 0;
+    int64_t a1 = 0, a2 = 0, q0 = 0;
     int32_t carry = 0;
     for (int base = 0; base < v.W; base += 64 * kWpl) {
         const int k0 = base + lane * kWpl;
         const int nw = max(0, min(kWpl, v.W - k0));  // words of this lane
+        uint32_t wd[kWpl] = {0u, 0u, 0u, 0u};
+        if (vec && nw == kWpl) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(row + k0);
+            wd[0] = q.x; wd[1] = q.y; wd[2] = q.z; wd[3] = q.w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < kWpl; ++t)
+                if (t < nw) wd[t] = row[k0 + t];
+        }
         // heights relative to the first site of the lane's segment
-        int32_t B = 0, S1 = 0, S2 = 0;
-        if (nw > 0) {
-            int g = gws + k0;
-            if (g >= v.W) g -= v.W;
-            uint32_t lo = row[g];
+        int32_t B = 0, S1 = 0, S2 = 0, qrel = 0;
+        bool hasq = false;
 #pragma unroll
-            for (int t = 0; t < kWpl; ++t) {
-                if (t < nw) {
-                    int g1 = g + 1;
-                    if (g1 == v.W) g1 = 0;
-                    const uint32_t hi = row[g1];
-                    const uint32_t word = __builtin_amdgcn_alignbit(hi, lo, off);
+        for (int t = 0; t < kWpl; ++t) {
+            if (t < nw) {
+                const uint32_t word = wd[t];
+                if (k0 + t == wq) {  // Q(xs0) inside this word
+                    const uint32_t below = bq ? (word & ((1u << bq) - 1u)) : 0u;
+                    qrel = B + 2 * (int32_t)__popc(below) - (int32_t)bq;
+                    hasq = true;
+                }
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint32_t e = lut[(word >> (8 * j)) & 255u];
-                        const int32_t s2 = (int32_t)(e & 0xffu);
-                        const int32_t s1 = (int32_t)(int8_t)(e >> 8);
-                        const int32_t d = (int32_t)(int8_t)(e >> 16);
-                        const int32_t t1 = 8 * B + s1;
-                        S1 += t1;
-                        S2 += B * (t1 + s1) + s2;
-                        B += d;
-                    }
-                    lo = hi;
-                    g = g1;
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t e = lut[(word >> (8 * j)) & 255u];
+                    const int32_t s2 = (int32_t)(e & 0xffu);
+                    const int32_t s1 = (int32_t)(int8_t)(e >> 8);
+                    const int32_t d = (int32_t)(int8_t)(e >> 16);
+                    const int32_t t1 = 8 * B + s1;
+                    S1 += t1;
+                    S2 += B * (t1 + s1) + s2;
+                    B += d;
                 }
             }
         }
@@ -91,22 +103,25 @@ __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
             const int32_t t = __shfl_up(incl, o, 64);
             if (lane >= o) incl += t;
         }
-        const int64_t b = carry + incl - B;  // P_y at the segment's first site
+        const int64_t b = carry + incl - B;  // Q at the segment's first site
         const int64_t n = 32 * nw;
         a1 += n * b + S1;
         a2 += n * b * b + 2 * b * S1 + S2;
+        if (hasq) q0 = b + qrel;
         carry += __shfl(incl, 63, 64);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         a1 += __shfl_down(a1, o, 64);
         a2 += __shfl_down(a2, o, 64);
+        q0 += __shfl_down(q0, o, 64);  // one lane holds Q(xs0)
     }
     if (lane == 0) {
+        const int64_t L = v.Lx;
         const uint32_t *rowy = v.planes + ((size_t)v.Ly + y) * v.W;
-        const uint32_t cb = (rowy[xs0 >> 5] >> (xs0 & 31)) & 1u;
-        rows[y] = a1;
-        rows[(size_t)v.Ly + y] = a2;
+        const uint32_t cb = (rowy[wq] >> bq) & 1u;
+        rows[y] = a1 - L * q0;
+        rows[(size_t)v.Ly + y] = a2 - 2 * q0 * a1 + L * q0 * q0;
         rows[2 * (size_t)v.Ly + y] = (int64_t)cb;
     }
 }
