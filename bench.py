@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=0.005,
                     help="ensemble leg: fraction of the full t = 20 L^1.6 (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving leg: jobs (0 skips it)")
+    ap.add_argument("--psd-calls", type=int, default=3,
+                    help="spectrum of the final surface: timed calls (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent "
@@ -274,6 +276,15 @@ def main():
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
         "w2_last": w2[-1] if w2 else None,
     }
+    if args.psd_calls > 0 and L & (L - 1) == 0:
+        sim.psd()  # the first call allocates its scratch
+        t0 = time.perf_counter()
+        for _ in range(args.psd_calls):
+            sx, sy = sim.psd()
+        psd_ms = 1e3 * (time.perf_counter() - t0) / args.psd_calls
+        out["psd"] = {"L": L, "t": t_hi, "ms_per_call": psd_ms, "calls": args.psd_calls,
+                      "S_direction_avg_n1_n2": [0.5 * (sx[1] + sy[1]), 0.5 * (sx[2] + sy[2])]}
+        log(f"spectrum: {psd_ms:.3f} ms per call")
     sim.free()
     del buf
     torch.cuda.synchronize()

@@ -78,6 +78,19 @@ int okpz_width(okpz_sim *s, int64_t t, int64_t *sum_h, int64_t *sum_h2);
  * from the exact integer numerator N*S2 - S1^2 (independent of H0). */
 int okpz_w2(okpz_sim *s, double *w2);
 
+/* Power spectrum density of the current surface along the two lattice axes
+ * (Sec. III, Eq. (PSD) with h(k) of Eq. (hF), d = 2, normalised by
+ * (Lx*Ly)^(-1/2)): sx[n] = |h(k)|^2 at k = (2 pi n/Lx, 0) for n = 0..Lx/2 and
+ * sy[n] at k = (0, 2 pi n/Ly) for n = 0..Ly/2; sx[0] = sy[0] = 0 (the mean
+ * height is subtracted).  One surface: the ensemble average of Eq. (PSD) and
+ * the average over the two directions are the caller's means over calls and
+ * over sx, sy.  sx and sy are host arrays of Lx/2+1 and Ly/2+1 doubles; either
+ * may be NULL.  The profiles are exact integers; the transform is fp64.
+ * Both sides must be powers of two (OKPZ_EINVAL otherwise).  The first call
+ * allocates at most min(32 MiB, Lx*Ly/4) + 40*max(Lx,Ly) bytes (plus
+ * alignment) of device scratch, kept until okpz_free.  Synchronous. */
+int okpz_psd(okpz_sim *s, double *sx, double *sy);
+
 /* Current time in MCS, and the absolute height H0 = h(0,0) (synchronous). */
 int okpz_time(const okpz_sim *s, int64_t *t);
 int okpz_h0(okpz_sim *s, int64_t *h0);

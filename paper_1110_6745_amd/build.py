@@ -4,7 +4,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.hip", "sweep.hip", "width.hip", "batch.hip"]
+SOURCES = ["api.hip", "sweep.hip", "width.hip", "psd.hip", "batch.hip"]
 LIB = os.path.join(HERE, "libokpz.so")
 
 

@@ -32,6 +32,7 @@ struct okpz_sim {
     void *mem;
     bool own_mem;
     int threads;  // sweep workgroup size (execution mapping only)
+    void *psd_mem;  // spectrum scratch, allocated by the first okpz_psd
 };
 
 namespace {
@@ -123,6 +124,7 @@ void release(okpz_sim *s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
+    if (s->psd_mem) (void)hipFree(s->psd_mem);
     if (s->own_mem && s->mem) (void)hipFree(s->mem);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -439,6 +441,32 @@ int okpz_w2(okpz_sim *s, double *w2)
     const __int128 N = (__int128)s->Lx * s->Ly;
     const __int128 num = N * S2r - S1r * S1r;  // independent of H0
     *w2 = (double)num / ((double)N * (double)N);
+    return OKPZ_OK;
+}
+
+int okpz_psd(okpz_sim *s, double *sx, double *sy)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    if (!okpz::psd_shape_ok(s->Lx, s->Ly))
+        return fail(OKPZ_EINVAL, "the spectrum needs power-of-two sides (lattice %lldx%lld)",
+                    (long long)s->Lx, (long long)s->Ly);
+    const okpz::PsdPlan p = okpz::psd_plan(s->Lx, s->Ly);
+    if (!s->psd_mem) {
+        hipError_t e = hipMalloc(&s->psd_mem, p.bytes);
+        if (e != hipSuccess) {
+            s->psd_mem = nullptr;
+            return fail(OKPZ_ENOMEM, "hipMalloc(%zu): %s", p.bytes, hipGetErrorString(e));
+        }
+    }
+    okpz::LatticeView v{s->buf[s->cur], (int32_t)s->Lx, (int32_t)s->Ly, s->W, s->ox};
+    HIP_TRY(okpz::launch_width_rows(v, s->d_rows, s->stream));
+    HIP_TRY(okpz::launch_psd(v, p, s->d_rows, s->psd_mem, s->stream));
+    const double *spec =
+        reinterpret_cast<const double *>(static_cast<const char *>(s->psd_mem) + p.off_spec);
+    const size_t nx = (size_t)s->Lx / 2 + 1, ny = (size_t)s->Ly / 2 + 1;
+    if (sx) HIP_TRY(hipMemcpyAsync(sx, spec, nx * 8, hipMemcpyDeviceToHost, s->stream));
+    if (sy) HIP_TRY(hipMemcpyAsync(sy, spec + nx, ny * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
     return OKPZ_OK;
 }
 

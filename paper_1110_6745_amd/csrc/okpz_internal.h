@@ -85,5 +85,20 @@ bool sweep_threads_ok(int threads);
 hipError_t launch_width(const LatticeView &v, int64_t *rows, int64_t *out, hipStream_t st);
 
 size_t width_scratch_words(int64_t Ly);
+// The per-row pass alone (rows[0..3 Ly) as above, no combine).
+hipError_t launch_width_rows(const LatticeView &v, int64_t *rows, hipStream_t st);
+
+// Power spectrum along the lattice axes (power-of-two sides): scratch layout
+// (byte offsets into one device allocation of `bytes`) and launch.  Needs the
+// rows of launch_width_rows; leaves S along x (Lx/2+1 doubles) followed by S
+// along y (Ly/2+1 doubles) at off_spec.
+struct PsdPlan {
+    int32_t R, nch;  // rows per column-count chunk, number of chunks
+    size_t off_cnt, off_zx, off_zy, off_spec, bytes;
+};
+bool psd_shape_ok(int64_t Lx, int64_t Ly);
+PsdPlan psd_plan(int64_t Lx, int64_t Ly);
+hipError_t launch_psd(const LatticeView &v, const PsdPlan &p, const int64_t *rows, void *scratch,
+                      hipStream_t st);
 
 }  // namespace okpz

@@ -30,11 +30,18 @@ __global__ __launch_bounds__(kFinalThreads) void width_final_kernel(const int64_
 
 size_t width_scratch_words(int64_t Ly) { return 3 * (size_t)Ly + 4; }
 
-hipError_t launch_width(const LatticeView &v, int64_t *rows, int64_t *out, hipStream_t st)
+hipError_t launch_width_rows(const LatticeView &v, int64_t *rows, hipStream_t st)
 {
     const int rpb = kRowThreads / 64;
     hipLaunchKernelGGL(width_rows_kernel, dim3((v.Ly + rpb - 1) / rpb), dim3(kRowThreads), 0, st, v,
                        rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_width(const LatticeView &v, int64_t *rows, int64_t *out, hipStream_t st)
+{
+    const hipError_t e = launch_width_rows(v, rows, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(width_final_kernel, dim3(1), dim3(kFinalThreads), 0, st, rows, v.Lx, v.Ly,
                        out);
     return hipGetLastError();

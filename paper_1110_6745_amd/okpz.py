@@ -62,6 +62,7 @@ _sig("okpz_init_on", ctypes.c_int, ctypes.POINTER(_vp), _i64, _i64, ctypes.c_dou
 _sig("okpz_sweep", ctypes.c_int, _vp, _i64)
 _sig("okpz_width", ctypes.c_int, _vp, _i64, _i64p, _i64p)
 _sig("okpz_w2", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double))
+_sig("okpz_psd", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 _sig("okpz_time", ctypes.c_int, _vp, _i64p)
 _sig("okpz_h0", ctypes.c_int, _vp, _i64p)
 _sig("okpz_stream", _vp, _vp)
@@ -116,7 +117,7 @@ _sig("okpz_serve_stats", ctypes.c_int, _vp, _i64p, ctypes.POINTER(ctypes.c_doubl
 _sig("okpz_serve_free", ctypes.c_int, _vp)
 
 EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on", "okpz_sweep",
-            "okpz_width", "okpz_w2", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
+            "okpz_width", "okpz_w2", "okpz_psd", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
             "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads", "okpz_sync",
             "okpz_free", "okpz_last_error", "okpz_batch_create", "okpz_batch_set_mapping",
             "okpz_batch_get_mapping", "okpz_batch_autotune", "okpz_batch_run",
@@ -203,6 +204,17 @@ class Sim:
         v = ctypes.c_double()
         _check(_lib.okpz_w2(self._h, ctypes.byref(v)))
         return v.value
+
+    def psd(self) -> tuple:
+        """(Sx, Sy): the surface's power spectrum along the x axis for
+        k = 2 pi n / Lx, n = 0 .. Lx/2, and along the y axis for n = 0 .. Ly/2
+        (Eqs. (PSD), (hF); power-of-two sides)."""
+        Lx, Ly = self.Lx, self.Ly
+        sx = np.empty(Lx // 2 + 1, dtype=np.float64)
+        sy = np.empty(Ly // 2 + 1, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.okpz_psd(self._h, sx.ctypes.data_as(dp), sy.ctypes.data_as(dp)))
+        return sx, sy
 
     def time(self) -> int:
         t = ctypes.c_int64()
