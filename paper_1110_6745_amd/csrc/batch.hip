@@ -970,7 +970,8 @@ struct ServeJob {
 size_t job_bytes(const okpz_job &j, size_t nsamp)
 {
     const size_t lat = al(2 * (size_t)j.Ly * (size_t)(j.Lx / 32) * 4);
-    return 2 * lat + al(8) + al((3 * (size_t)j.Ly + 4) * 8) + al(6 * 8 * std::max<size_t>(1, nsamp)) +
+    return 2 * lat + al(8) + al((okpz::width_scratch_words(j.Ly) + 4) * 8) +
+           al(6 * 8 * std::max<size_t>(1, nsamp)) +
            al(4 * std::max<size_t>(1, nsamp));
 }
 
@@ -1090,7 +1091,7 @@ int admit(okpz_server *sv, ServeJob &J, int slot, double t)
     d.buf[1] = reinterpret_cast<uint32_t *>(p + lat);
     d.h0 = reinterpret_cast<int64_t *>(p + 2 * lat);
     d.rows = reinterpret_cast<int64_t *>(p + 2 * lat + al(8));
-    const size_t rows_b = al((3 * (size_t)j.Ly + 4) * 8);
+    const size_t rows_b = al((okpz::width_scratch_words(j.Ly) + 4) * 8);
     d.samples = reinterpret_cast<int64_t *>(p + 2 * lat + al(8) + rows_b);
     int32_t *tt = reinterpret_cast<int32_t *>(p + 2 * lat + al(8) + rows_b +
                                                al(6 * 8 * std::max<size_t>(1, d.nsamp)));
@@ -1158,7 +1159,7 @@ int run_grid(okpz_server *sv, ServeJob &J, int64_t stop)
         J.s += 1;
         if (J.next_sample < d.nsamp && J.times[J.next_sample] == J.s) {
             const okpz::LatticeView v{d.buf[J.cur], d.Lx, d.Ly, d.W, J.ox};
-            int64_t *out = d.rows + 3 * (size_t)d.Ly;
+            int64_t *out = d.rows + okpz::width_scratch_words(d.Ly);
             e = okpz::launch_width(v, d.rows, out, sv->grid_stream);
             if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "serve width: %s", hipGetErrorString(e));
             hipLaunchKernelGGL(okpz::batch::record_sample_kernel, dim3(1), dim3(64), 0,

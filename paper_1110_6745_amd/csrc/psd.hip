@@ -14,13 +14,14 @@
 // radix-2 decimation-in-frequency FFT in fp64: global passes while a
 // butterfly's span exceeds the LDS tile, then one LDS-resident pass per tile;
 // the output stays in bit-reversed order and the spectrum kernel reads it so.
-#include "okpz_internal.h"
+#include "width_core.h"
 
 namespace okpz {
 namespace {
 
 constexpr int kCountThreads = 256;
 constexpr int kScanThreads = 1024;
+constexpr int kProfThreads = 256;
 constexpr int kFftThreads = 256;
 constexpr int kTile = 4096;          // complex fp64 values per LDS tile (64 KiB)
 constexpr int kTargetThreads = 1 << 18;
@@ -112,64 +113,92 @@ __global__ void colsum_kernel(const int32_t *partial, int32_t nch, int32_t Lx, i
     cnt[c] = s;
 }
 
-// One workgroup turns a sequence of integer steps d(i) into the profile
-// v(i) = scale * sum_{i'<i} d(i') + e(i), and writes v(i) - mean(v) into the
-// real parts of z (imaginary parts 0).  kRows = false: the column profile X
-// (d(l) = 2 c(stored column of l) - Ly, scale 1, e = 0); kRows = true: the
-// row profile Y (d(y) = 2 sigma_y-bit(0,y) - 1, scale Lx, e(y) = the row's
-// sum of P).  Every v is an integer below 2^41 in magnitude, exact in fp64.
+// The profiles as scans of integer steps d(i):
+//   v(i) = scale * sum_{i'<i} d(i') + e(i),
+// column profile X: d(l) = 2 c(stored column of l) - Ly, scale 1, e = 0;
+// row profile Y: d(y) = 2 sigma_y-bit(0,y) - 1, scale Lx, e(y) = the row's
+// sum of P.  Every v is an integer below 2^41 in magnitude, exact in fp64.
+// Three launches over blocks of kProfThreads values: block sums of d and of
+// v's contributions (sum_i v(i) = scale sum_j d(j) (n-1-j) + sum_j e(j)); one
+// workgroup scans the block sums and forms the mean; every block rescans its
+// values and writes v(i) - mean into the real parts of z.
 template <bool kRows>
-__global__ __launch_bounds__(kScanThreads) void profile_kernel(const int32_t *cnt,
-                                                               const int64_t *rows, int32_t Lx,
-                                                               int32_t Ly, int32_t ox, double2 *z)
+__device__ __forceinline__ int64_t profile_step(const int32_t *cnt, const int64_t *rows, int32_t Lx,
+                                                int32_t Ly, int32_t ox, int i)
 {
-    __shared__ int64_t lds[64];
-    __shared__ double mean_s;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = kScanThreads >> 6;
+    if (kRows) return 2 * rows[2 * (size_t)Ly + i] - 1;
+    int xs = i - ox;
+    if (xs < 0) xs += Lx;
+    return 2 * (int64_t)cnt[xs] - Ly;
+}
+
+// blk[2 b] = sum of d over block b, blk[2 b + 1] = its part of sum_i v(i).
+template <bool kRows>
+__global__ __launch_bounds__(kProfThreads) void profile_sums_kernel(const int32_t *cnt,
+                                                                    const int64_t *rows, int32_t Lx,
+                                                                    int32_t Ly, int32_t ox,
+                                                                    int64_t *blk)
+{
+    __shared__ int64_t lds[32];
     const int n = kRows ? Ly : Lx;
     const int64_t scale = kRows ? (int64_t)Lx : 1;
-    auto step = [&](int i) -> int64_t {
-        if (kRows) return 2 * rows[2 * (size_t)Ly + i] - 1;
-        int xs = i - ox;
-        if (xs < 0) xs += Lx;
-        return 2 * (int64_t)cnt[xs] - Ly;
-    };
-    const int per = (n + kScanThreads - 1) / kScanThreads;
-    const int a = min(n, tid * per), b = min(n, a + per);
+    const int i = blockIdx.x * kProfThreads + threadIdx.x;
+    const int64_t d = i < n ? profile_step<kRows>(cnt, rows, Lx, Ly, ox, i) : 0;
+    const int64_t e = (kRows && i < n) ? rows[i] : 0;
+    const int64_t w = i < n ? scale * d * (int64_t)(n - 1 - i) + e : 0;
+    const __int128 D = core::block_sum_i128(d, lds);
+    const __int128 V = core::block_sum_i128(w, lds);
+    if (threadIdx.x == 0) {
+        blk[2 * (size_t)blockIdx.x] = (int64_t)D;
+        blk[2 * (size_t)blockIdx.x + 1] = (int64_t)V;
+    }
+}
 
-    int64_t local = 0;
-    for (int i = a; i < b; ++i) local += step(i);
-    int64_t incl = local;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
+// In place: blk[2 b] becomes the exclusive prefix of the block sums of d;
+// blk[2 nb] receives the mean of v as the bits of a double.
+__global__ __launch_bounds__(kScanThreads) void profile_offsets_kernel(int64_t *blk, int32_t nb,
+                                                                       int32_t n)
+{
+    __shared__ int64_t lds[32];
+    const int per = (nb + kScanThreads - 1) / kScanThreads;
+    const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+    int64_t local = 0, vs = 0;
+    for (int b = b0; b < b1; ++b) {
+        local += blk[2 * (size_t)b];
+        vs += blk[2 * (size_t)b + 1];
     }
-    if (lane == 63) lds[wave] = incl;
-    __syncthreads();
-    int64_t run = incl - local;
-    for (int w = 0; w < wave; ++w) run += lds[w];
+    int64_t unused;
+    int64_t run = core::block_exclusive_scan(local, lds, &unused);
+    const __int128 V = core::block_sum_i128(vs, lds);
+    for (int b = b0; b < b1; ++b) {
+        const int64_t d = blk[2 * (size_t)b];
+        blk[2 * (size_t)b] = run;
+        run += d;
+    }
+    if (threadIdx.x == 0) {
+        const double mean = (double)(int64_t)V / n;  // its rounding only moves n = 0
+        blk[2 * (size_t)nb] = __double_as_longlong(mean);
+    }
+}
 
-    int64_t vs = 0;
-    for (int i = a; i < b; ++i) {
-        const int64_t v = scale * run + (kRows ? rows[i] : 0);
-        z[i] = make_double2((double)v, 0.0);
-        vs += v;
-        run += step(i);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) vs += __shfl_down(vs, o, 64);
-    __syncthreads();  // the scan totals were read above
-    if (lane == 0) lds[wave] = vs;
-    __syncthreads();
-    if (tid == 0) {
-        int64_t tot = 0;
-        for (int w = 0; w < nwave; ++w) tot += lds[w];
-        mean_s = (double)tot / n;  // its rounding only moves the n = 0 value
-    }
-    __syncthreads();
-    const double mean = mean_s;
-    for (int i = a; i < b; ++i) z[i].x -= mean;
+template <bool kRows>
+__global__ __launch_bounds__(kProfThreads) void profile_write_kernel(const int32_t *cnt,
+                                                                     const int64_t *rows,
+                                                                     int32_t Lx, int32_t Ly,
+                                                                     int32_t ox, const int64_t *blk,
+                                                                     int32_t nb, double2 *z)
+{
+    __shared__ int64_t lds[16];
+    const int n = kRows ? Ly : Lx;
+    const int64_t scale = kRows ? (int64_t)Lx : 1;
+    const int i = blockIdx.x * kProfThreads + threadIdx.x;
+    const int64_t d = i < n ? profile_step<kRows>(cnt, rows, Lx, Ly, ox, i) : 0;
+    int64_t unused;
+    const int64_t pre = blk[2 * (size_t)blockIdx.x] + core::block_exclusive_scan(d, lds, &unused);
+    if (i >= n) return;
+    const int64_t v = scale * pre + (kRows ? rows[i] : 0);
+    const double mean = __longlong_as_double(blk[2 * (size_t)nb]);
+    z[i] = make_double2((double)v - mean, 0.0);
 }
 
 // z <- (z + w) at i, (z - w) e^{-i pi (i mod 2h) / h} at i + h: one radix-2
@@ -269,7 +298,9 @@ PsdPlan psd_plan(int64_t Lx, int64_t Ly)
     p.off_zx = p.off_cnt + al((size_t)Lx * 4);
     p.off_zy = p.off_zx + al((size_t)Lx * 16);
     p.off_spec = p.off_zy + al((size_t)Ly * 16);
-    p.bytes = p.off_spec + al((size_t)(Lx / 2 + 1 + Ly / 2 + 1) * 8);
+    p.off_blk = p.off_spec + al((size_t)(Lx / 2 + 1 + Ly / 2 + 1) * 8);
+    const size_t nbx = (Lx + kProfThreads - 1) / kProfThreads, nby = (Ly + kProfThreads - 1) / kProfThreads;
+    p.bytes = p.off_blk + al((2 * (nbx + nby) + 4) * 8);
     return p;
 }
 
@@ -288,10 +319,20 @@ hipError_t launch_psd(const LatticeView &v, const PsdPlan &p, const int64_t *row
                        dim3(kCountThreads), 0, st, v.planes, v.Ly, v.W, p.R, p.nch, partial);
     hipLaunchKernelGGL(colsum_kernel, dim3((v.Lx + 255) / 256), dim3(256), 0, st, partial, p.nch,
                        v.Lx, cnt);
-    hipLaunchKernelGGL(profile_kernel<false>, dim3(1), dim3(kScanThreads), 0, st, cnt, rows, v.Lx,
-                       v.Ly, v.ox, zx);
-    hipLaunchKernelGGL(profile_kernel<true>, dim3(1), dim3(kScanThreads), 0, st, cnt, rows, v.Lx,
-                       v.Ly, v.ox, zy);
+    const int32_t nbx = (v.Lx + kProfThreads - 1) / kProfThreads;
+    const int32_t nby = (v.Ly + kProfThreads - 1) / kProfThreads;
+    int64_t *bx = reinterpret_cast<int64_t *>(base + p.off_blk);
+    int64_t *by = bx + 2 * (size_t)nbx + 2;
+    hipLaunchKernelGGL(profile_sums_kernel<false>, dim3(nbx), dim3(kProfThreads), 0, st, cnt, rows,
+                       v.Lx, v.Ly, v.ox, bx);
+    hipLaunchKernelGGL(profile_sums_kernel<true>, dim3(nby), dim3(kProfThreads), 0, st, cnt, rows,
+                       v.Lx, v.Ly, v.ox, by);
+    hipLaunchKernelGGL(profile_offsets_kernel, dim3(1), dim3(kScanThreads), 0, st, bx, nbx, v.Lx);
+    hipLaunchKernelGGL(profile_offsets_kernel, dim3(1), dim3(kScanThreads), 0, st, by, nby, v.Ly);
+    hipLaunchKernelGGL(profile_write_kernel<false>, dim3(nbx), dim3(kProfThreads), 0, st, cnt, rows,
+                       v.Lx, v.Ly, v.ox, bx, nbx, zx);
+    hipLaunchKernelGGL(profile_write_kernel<true>, dim3(nby), dim3(kProfThreads), 0, st, cnt, rows,
+                       v.Lx, v.Ly, v.ox, by, nby, zy);
     hipError_t e = launch_fft(zx, v.Lx, st);
     if (e != hipSuccess) return e;
     e = launch_fft(zy, v.Ly, st);

@@ -126,6 +126,56 @@ __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
     }
 }
 
+// Exclusive prefix sum of v over the workgroup in thread order; *total gets
+// the workgroup's sum.  lds: 16 entries.  Ends with a barrier.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *lds, int64_t *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    int64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+    for (int w = 0; w < nwave; ++w) {
+        const int64_t s = lds[w];
+        if (w < wave) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+// Sum of a 128-bit value over the workgroup, returned in every thread.
+// lds: 32 entries.  Ends with a barrier.
+__device__ __forceinline__ __int128 block_sum_i128(__int128 v, int64_t *lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    uint64_t lo = (uint64_t)v, hi = (uint64_t)((unsigned __int128)v >> 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t alo = __shfl_down(lo, o, 64), ahi = __shfl_down(hi, o, 64);
+        const unsigned __int128 s = (((unsigned __int128)hi << 64) | lo) +
+                                    (((unsigned __int128)ahi << 64) | alo);
+        lo = (uint64_t)s;
+        hi = (uint64_t)(s >> 64);
+    }
+    if (lane == 0) {
+        lds[2 * wave] = (int64_t)lo;
+        lds[2 * wave + 1] = (int64_t)hi;
+    }
+    __syncthreads();
+    unsigned __int128 t = 0;
+    for (int w = 0; w < nwave; ++w)
+        t += ((unsigned __int128)(uint64_t)lds[2 * w + 1] << 64) | (uint64_t)lds[2 * w];
+    __syncthreads();
+    return (__int128)t;
+}
+
 // Combine the rows into out[0..3] = {S1' lo, S1' hi, S2' lo, S2' hi} (128-bit
 // two's complement halves) with one workgroup of up to 1024 threads.  Each
 // thread takes a run of rows; the column-0 prefix G(y) comes from a
