@@ -57,14 +57,14 @@ def lib() -> ctypes.CDLL:
     L.or_block_sweep.argtypes = [_u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
-                                 ctypes.c_int32, _i64p, _i64p, _i64p, _u8p]
+                                 ctypes.c_int32, _i64p, _i64p, _i64p, _u8p, ctypes.c_int]
     L.or_block_sweep.restype = ctypes.c_int
     L.or_block_shift.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
                                  ctypes.c_int32, _i32p, _i32p]
     L.or_block_shift.restype = None
     L.or_sweep.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                            ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _i64p,
-                           _i64p, _i64p, ctypes.c_int]
+                           _i64p, _i64p, ctypes.c_int, ctypes.c_int]
     L.or_sweep.restype = ctypes.c_int
     L.or_rsu_sweep.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _i64p,
@@ -147,18 +147,22 @@ class Counts:
 
 
 def sweep(lat: np.ndarray, p: float, q: float, seed: int, s: int, H0: int,
-          check: bool = False, counts: Counts | None = None) -> int:
+          check: bool = False, counts: Counts | None = None, delayed: bool = False) -> int:
     """One MCS (sweep index ``s``) of the tiled dynamics, in place.
 
     Returns the new absolute height of site (0,0).  ``check`` turns on the
-    bond-conflict checker (raises if any bond is touched twice in one step).
+    bond-conflict checker (raises if any bond is touched twice in one step,
+    or in one phase of a step with ``delayed``).  ``delayed`` selects the
+    delayed thread-cell borders of Sec. II (bulk, then edge, then corner
+    attempts of every step) instead of dead ones.
     """
     _check_lattice(lat)
     Ly, Lx = lat.shape
     h = ctypes.c_int64(H0)
     a, d = ctypes.c_int64(0), ctypes.c_int64(0)
     rc = lib().or_sweep(_ptr(lat, _u8p), Lx, Ly, threshold(p), threshold(q), seed, s,
-                        ctypes.byref(h), ctypes.byref(a), ctypes.byref(d), int(check))
+                        ctypes.byref(h), ctypes.byref(a), ctypes.byref(d), int(check),
+                        int(delayed))
     if rc == -1:
         raise AssertionError("bond conflict inside one step of the tiled schedule")
     if rc != 0:
@@ -170,15 +174,15 @@ def sweep(lat: np.ndarray, p: float, q: float, seed: int, s: int, H0: int,
 
 
 def run(lat: np.ndarray, p: float, q: float, seed: int, t0: int, n: int, H0: int,
-        check: bool = False, counts: Counts | None = None) -> int:
+        check: bool = False, counts: Counts | None = None, delayed: bool = False) -> int:
     """Sweeps ``t0 .. t0+n-1`` of the tiled dynamics; returns the new H0."""
     for s in range(t0, t0 + n):
-        H0 = sweep(lat, p, q, seed, s, H0, check=check, counts=counts)
+        H0 = sweep(lat, p, q, seed, s, H0, check=check, counts=counts, delayed=delayed)
     return H0
 
 
 def block_sweep(blk: np.ndarray, C: int, seed: int, s: int, block_id: int, p: float,
-                q: float, site00=(-1, -1), check: bool = False) -> tuple:
+                q: float, site00=(-1, -1), check: bool = False, delayed: bool = False) -> tuple:
     """One sweep of a single device-level block given as its (By, Bx) cut-out.
 
     Returns (dh00, n_att, n_det).  Blocks are independent within a sweep, so
@@ -191,7 +195,9 @@ def block_sweep(blk: np.ndarray, C: int, seed: int, s: int, block_id: int, p: fl
     rc = lib().or_block_sweep(_ptr(blk, _u8p), Bx, By, C, seed, s, block_id,
                               threshold(p), threshold(q), site00[0], site00[1],
                               ctypes.byref(dh), ctypes.byref(a), ctypes.byref(d),
-                              _ptr(touched, _u8p) if check else None)
+                              _ptr(touched, _u8p) if check else None, int(delayed))
+    if rc == -2:
+        raise ValueError("delayed cell borders need a cell side of at least 2")
     if rc != 0:
         raise AssertionError("bond conflict inside one step of the tiled schedule")
     return dh.value, a.value, d.value
@@ -245,11 +251,14 @@ def w2(S1: int, S2: int, N: int) -> float:
 
 
 def ensemble(Lx: int, Ly: int, p: float, q: float, seed0: int, R: int, tmax: int,
-             rsu: bool = False) -> np.ndarray:
+             rsu: bool = False, delayed: bool = False) -> np.ndarray:
     """(S1, S2) after every MCS t = 1..tmax of R flat-start realizations with
-    seeds seed0 .. seed0+R-1; returns an int64 array of shape (R, tmax, 2)."""
+    seeds seed0 .. seed0+R-1; returns an int64 array of shape (R, tmax, 2).
+    ``rsu`` selects the random-sequential judge, ``delayed`` the tiled
+    dynamics with delayed cell borders."""
     out = np.zeros((R, tmax, 2), dtype=np.int64)
-    rc = lib().or_ensemble(Lx, Ly, float(p), float(q), seed0, R, tmax, int(rsu),
+    kind = 1 if rsu else (2 if delayed else 0)
+    rc = lib().or_ensemble(Lx, Ly, float(p), float(q), seed0, R, tmax, kind,
                            _ptr(out, _i64p))
     if rc != 0:
         raise RuntimeError(f"or_ensemble failed ({rc})")

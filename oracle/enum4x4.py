@@ -14,7 +14,11 @@ transition matrices of
   one 4x4 thread cell, Sec. II): per MCS a uniform block shift, then C^2 = 16
   steps, each with a uniform cell origin and one site drawn among the cell's
   (C-1)^2 = 9 active sites with the exact probabilities of the 16-bit draw
-  ``floor(h16 * 9 / 2^16)``; sites on the block's dead border do nothing.
+  ``floor(h16 * 9 / 2^16)``; sites on the block's dead border do nothing;
+* the same chain with delayed cell borders (Sec. II): the site is drawn among
+  all 16 sites of the cell (``floor(h16 * 16 / 2^16)``, exactly uniform);
+  with a single cell per block the bulk / edge / corner order of a step has
+  nothing to order, so only the draw and the block border matter.
 
 Both chains start from the flat zig-zag state (Sec. III) and give the exact
 law of W^2(t) (Eq. (Wdef)), against which Monte Carlo histograms of the C
@@ -196,22 +200,29 @@ def translation(dx: int, dy: int) -> np.ndarray:
     return perm
 
 
-def tiled_site_weights(C: int = 4) -> np.ndarray:
+def tiled_site_weights(C: int = 4, delayed: bool = False) -> np.ndarray:
     """Probability that a step attempts block-local site (u, v), shape (L, L);
     entries with u = 0 or v = 0 are dead-border no-ops."""
-    P = draw_probabilities(C)
+    if delayed:
+        h = np.arange(1 << 16, dtype=np.int64)
+        P = np.bincount((h * C * C) >> 16, minlength=C * C) / float(1 << 16)
+    else:
+        P = draw_probabilities(C)
     w = np.zeros((L, L))
     for oy in range(C):
         for ox in range(C):
             for i in range(len(P)):
-                a, b = 1 + i % (C - 1), 1 + i // (C - 1)
+                if delayed:
+                    a, b = i % C, i // C
+                else:
+                    a, b = 1 + i % (C - 1), 1 + i // (C - 1)
                 w[(oy + b) % L, (ox + a) % L] += P[i] / (C * C)
     return w
 
 
-def tiled_step_matrix(sx: int, sy: int, p: float, q: float) -> np.ndarray:
+def tiled_step_matrix(sx: int, sy: int, p: float, q: float, delayed: bool = False) -> np.ndarray:
     """One step of the tiled chain under block shift (sx, sy), built directly."""
-    w = tiled_site_weights()
+    w = tiled_site_weights(delayed=delayed)
     S = len(states())
     step = np.zeros((S, S))
     for v in range(L):
@@ -223,12 +234,12 @@ def tiled_step_matrix(sx: int, sy: int, p: float, q: float) -> np.ndarray:
     return step
 
 
-def tiled_mcs_matrix(p: float, q: float) -> np.ndarray:
+def tiled_mcs_matrix(p: float, q: float, delayed: bool = False) -> np.ndarray:
     """One MCS of the tiled chain on the 4x4 torus (B = C = 4): the average
     over the L*L block shifts of (step matrix)^(C*C).  The step under shift d
     is the shift-0 step conjugated by the translation by d."""
     C = 4
-    P16 = np.linalg.matrix_power(tiled_step_matrix(0, 0, p, q), C * C)
+    P16 = np.linalg.matrix_power(tiled_step_matrix(0, 0, p, q, delayed), C * C)
     total = np.zeros_like(P16)
     for sy in range(L):
         for sx in range(L):

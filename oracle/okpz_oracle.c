@@ -166,61 +166,87 @@ static int bit_to_slope(int bit) { return bit ? +1 : -1; }
 /* site00_u/v: block-local position of lattice site (0,0), or -1; *dh00      */
 /* accumulates its height change (the absolute height reference).            */
 /* touched: NULL, or 2*Bx*By bytes of scratch for the bond-conflict check.   */
-/* Returns 0, or -1 if a bond was touched twice within one step.            */
+/*                                                                          */
+/* delayed != 0 selects the delayed thread-cell borders of Sec. II instead   */
+/* of dead ones: each cell draws one of all C*C sites, i = floor(h16 C^2 /   */
+/* 2^16), a = i mod C, b = i div C; at every step the attempts on cell-bulk  */
+/* sites (a, b >= 1) come first, then those on the cell's edges (exactly one */
+/* of a, b zero), then those on its corner (a = b = 0).  Attempts of one     */
+/* phase are never nearest neighbours, so each phase is order independent;   */
+/* the conflict check covers one phase at a time.  Needs C >= 2.            */
+/* Returns 0, or -1 if a bond was touched twice within one step (phase).    */
 /* ------------------------------------------------------------------------ */
 int or_block_sweep(uint8_t *blk, int32_t Bx, int32_t By, int32_t C, uint64_t seed,
                    uint32_t s, uint32_t id, uint64_t Tp, uint64_t Tq,
                    int32_t site00_u, int32_t site00_v, int64_t *dh00,
-                   int64_t *n_att, int64_t *n_det, uint8_t *touched)
+                   int64_t *n_att, int64_t *n_det, uint8_t *touched, int delayed)
 {
     const int32_t ncx = Bx / C, ncy = By / C, ncell = ncx * ncy;
-    const uint32_t nact = (uint32_t)((C - 1) * (C - 1));
+    const uint32_t nact = delayed ? (uint32_t)(C * C) : (uint32_t)((C - 1) * (C - 1));
+    const int nphase = delayed ? 3 : 1;
+    int32_t su[1024], sv[1024], sph[1024];
+    if (ncell > 1024 || (delayed && C < 2)) return -2;
     for (int32_t k = 0; k < C * C; ++k) {
         uint32_t r[4];
         draw(seed, s, id, (uint32_t)(k / 2), TAG_ORIGIN, r);
         int32_t ox = (int32_t)uniform_below((k % 2 == 0) ? r[0] : r[2], (uint32_t)C);
         int32_t oy = (int32_t)uniform_below((k % 2 == 0) ? r[1] : r[3], (uint32_t)C);
-        if (touched) memset(touched, 0, (size_t)2 * Bx * By);
 
+        /* every cell's site of this step */
         for (int32_t c = 0; c < ncell; ++c) {
             int32_t cx = c % ncx, cy = c / ncx;
             draw(seed, s, id, ((uint32_t)(k / 8) << 16) | (uint32_t)c, TAG_SITE, r);
             int32_t e = k % 8;
             uint32_t h16 = (r[e / 2] >> (16 * (e % 2))) & 0xffffu;
             uint32_t idx = (uint32_t)(((uint64_t)h16 * nact) >> 16);
-            int32_t a = 1 + (int32_t)(idx % (uint32_t)(C - 1));
-            int32_t b = 1 + (int32_t)(idx / (uint32_t)(C - 1));
-            int32_t u = (ox + cx * C + a) % Bx;
-            int32_t v = (oy + cy * C + b) % By;
-            if (u == 0 || v == 0) continue; /* block-border site: no-op */
-
-            if (touched) {
-                /* bonds: x-bond stored at (u-1,v) and (u,v), y-bond at (u,v-1) and (u,v) */
-                size_t ia = (size_t)2 * (v * Bx + (u - 1)) + 0;
-                size_t ib = (size_t)2 * (v * Bx + u) + 0;
-                size_t ic = (size_t)2 * ((v - 1) * Bx + u) + 1;
-                size_t id_ = (size_t)2 * (v * Bx + u) + 1;
-                if (touched[ia] || touched[ib] || touched[ic] || touched[id_]) return -1;
-                touched[ia] = touched[ib] = touched[ic] = touched[id_] = 1;
+            int32_t a, b;
+            if (delayed) {
+                a = (int32_t)(idx % (uint32_t)C);
+                b = (int32_t)(idx / (uint32_t)C);
+            } else {
+                a = 1 + (int32_t)(idx % (uint32_t)(C - 1));
+                b = 1 + (int32_t)(idx / (uint32_t)(C - 1));
             }
+            su[c] = (ox + cx * C + a) % Bx;
+            sv[c] = (oy + cy * C + b) % By;
+            sph[c] = (a == 0) + (b == 0); /* 0 bulk, 1 edge, 2 corner */
+        }
 
-            uint8_t *sl = &blk[v * Bx + (u - 1)];
-            uint8_t *sc = &blk[v * Bx + u];
-            uint8_t *sd = &blk[(v - 1) * Bx + u];
-            int A = bit_to_slope(*sl & 1), B = bit_to_slope(*sc & 1);
-            int Cc = bit_to_slope((*sd >> 1) & 1), D = bit_to_slope((*sc >> 1) & 1);
-            int kind = site_kind(A, B, Cc, D);
-            if (kind == 0) continue;
+        for (int ph = 0; ph < nphase; ++ph) {
+            if (touched) memset(touched, 0, (size_t)2 * Bx * By);
+            for (int32_t c = 0; c < ncell; ++c) {
+                if (delayed && sph[c] != ph) continue;
+                int32_t u = su[c], v = sv[c];
+                if (u == 0 || v == 0) continue; /* block-border site: no-op */
 
-            draw(seed, s, id, ((uint32_t)(k / 4) << 16) | (uint32_t)c, TAG_ACCEPT, r);
-            uint64_t racc = r[k % 4];
-            int accept = (kind > 0) ? (racc < Tp) : (racc < Tq);
-            if (!accept) continue;
+                if (touched) {
+                    /* bonds: x-bond stored at (u-1,v) and (u,v), y-bond at (u,v-1) and (u,v) */
+                    size_t ia = (size_t)2 * (v * Bx + (u - 1)) + 0;
+                    size_t ib = (size_t)2 * (v * Bx + u) + 0;
+                    size_t ic = (size_t)2 * ((v - 1) * Bx + u) + 1;
+                    size_t id_ = (size_t)2 * (v * Bx + u) + 1;
+                    if (touched[ia] || touched[ib] || touched[ic] || touched[id_]) return -1;
+                    touched[ia] = touched[ib] = touched[ic] = touched[id_] = 1;
+                }
 
-            /* flip the four slopes: minimum <-> maximum */
-            *sl ^= 1; *sc ^= 1; *sd ^= 2; *sc ^= 2;
-            if (kind > 0) { if (n_att) (*n_att)++; } else { if (n_det) (*n_det)++; }
-            if (u == site00_u && v == site00_v && dh00) *dh00 += (kind > 0) ? 2 : -2;
+                uint8_t *sl = &blk[v * Bx + (u - 1)];
+                uint8_t *sc = &blk[v * Bx + u];
+                uint8_t *sd = &blk[(v - 1) * Bx + u];
+                int A = bit_to_slope(*sl & 1), B = bit_to_slope(*sc & 1);
+                int Cc = bit_to_slope((*sd >> 1) & 1), D = bit_to_slope((*sc >> 1) & 1);
+                int kind = site_kind(A, B, Cc, D);
+                if (kind == 0) continue;
+
+                draw(seed, s, id, ((uint32_t)(k / 4) << 16) | (uint32_t)c, TAG_ACCEPT, r);
+                uint64_t racc = r[k % 4];
+                int accept = (kind > 0) ? (racc < Tp) : (racc < Tq);
+                if (!accept) continue;
+
+                /* flip the four slopes: minimum <-> maximum */
+                *sl ^= 1; *sc ^= 1; *sd ^= 2; *sc ^= 2;
+                if (kind > 0) { if (n_att) (*n_att)++; } else { if (n_det) (*n_det)++; }
+                if (u == site00_u && v == site00_v && dh00) *dh00 += (kind > 0) ? 2 : -2;
+            }
         }
     }
     return 0;
@@ -247,10 +273,11 @@ void or_block_shift(uint64_t seed, uint32_t s, int32_t Bx, int32_t By,
 /* ------------------------------------------------------------------------ */
 int or_sweep(uint8_t *lat, int64_t Lx, int64_t Ly, uint64_t Tp, uint64_t Tq,
              uint64_t seed, uint32_t s, int64_t *H0, int64_t *n_att, int64_t *n_det,
-             int check)
+             int check, int delayed)
 {
     int32_t Bx, By, C;
     if (or_geometry(Lx, Ly, &Bx, &By, &C) != 0) return -2;
+    if (delayed && C < 2) return -2;
     int32_t sx, sy;
     or_block_shift(seed, s, Bx, By, &sx, &sy);
     const int64_t nbx = Lx / Bx, nby = Ly / By, nblk = nbx * nby;
@@ -272,7 +299,7 @@ int or_sweep(uint8_t *lat, int64_t Lx, int64_t Ly, uint64_t Tp, uint64_t Tq,
         int32_t sv = (u00 < Bx && v00 < By) ? (int32_t)v00 : -1;
         int64_t a = 0, d = 0, h = 0;
         if (or_block_sweep(blk, Bx, By, C, seed, s, (uint32_t)bid, Tp, Tq, su, sv, &h,
-                           &a, &d, touched) != 0)
+                           &a, &d, touched, delayed) != 0)
             bad = 1;
         for (int32_t v = 0; v < By; ++v)
             for (int32_t u = 0; u < Bx; ++u)
@@ -388,11 +415,12 @@ void or_set_num_threads(int n)
 /* ------------------------------------------------------------------------ */
 /* Ensemble driver for the statistical pins: R independent realizations     */
 /* (seed0 + r) from the flat state; after each MCS t = 1..tmax, stores      */
-/* (S1, S2) into out[(r*tmax + t-1)*2 + {0,1}].  rsu != 0 selects the       */
-/* random-sequential judge instead of the tiled dynamics.                    */
+/* (S1, S2) into out[(r*tmax + t-1)*2 + {0,1}].  kind: 0 the tiled dynamics */
+/* with dead cell borders, 1 the random-sequential judge, 2 the tiled        */
+/* dynamics with delayed cell borders.                                       */
 /* ------------------------------------------------------------------------ */
 int or_ensemble(int64_t Lx, int64_t Ly, double p, double q, uint64_t seed0, int64_t R,
-                int64_t tmax, int rsu, int64_t *out)
+                int64_t tmax, int kind, int64_t *out)
 {
     const uint64_t Tp = or_threshold(p), Tq = or_threshold(q);
     uint8_t *lat = (uint8_t *)malloc((size_t)(Lx * Ly));
@@ -401,10 +429,10 @@ int or_ensemble(int64_t Lx, int64_t Ly, double p, double q, uint64_t seed0, int6
         or_flat(lat, Lx, Ly);
         int64_t H0 = 0;
         for (int64_t t = 0; t < tmax; ++t) {
-            if (rsu) {
+            if (kind == 1) {
                 or_rsu_sweep(lat, Lx, Ly, Tp, Tq, seed0 + (uint64_t)r, (uint64_t)t, &H0, NULL, NULL);
             } else if (or_sweep(lat, Lx, Ly, Tp, Tq, seed0 + (uint64_t)r, (uint32_t)t, &H0, NULL,
-                                NULL, 0) != 0) {
+                                NULL, 0, kind == 2) != 0) {
                 free(lat);
                 return -1;
             }

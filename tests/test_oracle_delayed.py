@@ -1,0 +1,186 @@
+"""Pins of the oracle's delayed thread-cell borders (Sec. II): the cell's
+bulk sites first, then its edges, then its corner, at every step.
+
+* a direct Python transcription of one sweep (block by block, step by step,
+  the picks applied one at a time in (phase, cell) order) reproduces the C
+  oracle bit for bit, and applying the same picks in plain cell order does
+  not (so the phase order is exercised);
+* no bond is touched twice within one phase of a step (conflict checker);
+* Eq. (1) invariants: S1 - N/2 = 2 (attachments - detachments), q = 0 never
+  lowers the surface, p = q = 0 is the identity, the mirror symmetry
+  (complement the slopes, swap p and q) holds bit for bit;
+* on the 4x4 torus (one cell per block) the Monte Carlo law of W^2(t)
+  matches the exact master-equation law of the delayed chain.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import enum4x4 as E
+from tests import inputs
+from tests.test_oracle_exact4x4 import _histogram_test
+
+
+def python_sweep(lat, p, q, seed, s, H0, delayed=True, phase_order=True):
+    """One tiled sweep written out directly from the contract."""
+    Ly, Lx = lat.shape
+    Bx, By, C = oracle.geometry(Lx, Ly)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+
+    def ph(*ctr):
+        return oracle.philox(ctr, key)
+
+    def U(r, n):
+        return (r * n) >> 32
+
+    r = ph(s, 0, 0, 2)
+    sx, sy = U(r[0], Bx), U(r[1], By)
+    Tp, Tq = oracle.threshold(p), oracle.threshold(q)
+    nbx, nby = Lx // Bx, Ly // By
+    ncx, ncy = Bx // C, By // C
+    nsite = C * C if delayed else (C - 1) * (C - 1)
+    for j in range(nby):
+        for i in range(nbx):
+            bid = j * nbx + i
+            x0, y0 = sx + i * Bx, sy + j * By
+            for k in range(C * C):
+                r = ph(s, bid, k // 2, 1)
+                ox = U(r[0] if k % 2 == 0 else r[2], C)
+                oy = U(r[1] if k % 2 == 0 else r[3], C)
+                picks = []
+                for c in range(ncx * ncy):
+                    cx, cy = c % ncx, c // ncx
+                    w = ph(s, bid, ((k // 8) << 16) | c, 0)
+                    e = k % 8
+                    h16 = (w[e // 2] >> (16 * (e % 2))) & 0xFFFF
+                    idx = (h16 * nsite) >> 16
+                    if delayed:
+                        a, b = idx % C, idx // C
+                    else:
+                        a, b = 1 + idx % (C - 1), 1 + idx // (C - 1)
+                    phase = int(a == 0) + int(b == 0) if phase_order else 0
+                    picks.append((phase, c, (ox + cx * C + a) % Bx, (oy + cy * C + b) % By))
+                for _, c, u, v in sorted(picks):
+                    if u == 0 or v == 0:
+                        continue
+                    X, Y = (x0 + u) % Lx, (y0 + v) % Ly
+                    XL, YD = (X - 1) % Lx, (Y - 1) % Ly
+                    slopes = (1 if lat[Y, XL] & 1 else -1, 1 if lat[Y, X] & 1 else -1,
+                              1 if lat[YD, X] & 2 else -1, 1 if lat[Y, X] & 2 else -1)
+                    if slopes == (-1, 1, -1, 1):
+                        kind = 1
+                    elif slopes == (1, -1, 1, -1):
+                        kind = -1
+                    else:
+                        continue
+                    racc = ph(s, bid, ((k // 4) << 16) | c, 4)[k % 4]
+                    if racc >= (Tp if kind > 0 else Tq):
+                        continue
+                    lat[Y, XL] ^= 1
+                    lat[Y, X] ^= 3
+                    lat[YD, X] ^= 2
+                    if X == 0 and Y == 0:
+                        H0 += 2 * kind
+    return H0
+
+
+@pytest.mark.parametrize("Lx,Ly,delayed", [(16, 16, True), (32, 16, True), (96, 48, True),
+                                           (16, 16, False), (96, 48, False)])
+def test_python_transcription_matches(Lx, Ly, delayed):
+    for p, q, seed in [(1.0, 0.0, 3), (0.6, 0.5, 2**33 + 5)]:
+        lat0, H0 = inputs.rough_state(Lx, Ly, seed=seed % 100, mcs=2)
+        a, b = lat0.copy(), lat0.copy()
+        Ha = Hb = H0
+        for s in range(5, 8):
+            Ha = oracle.sweep(a, p, q, seed, s, Ha, check=True, delayed=delayed)
+            Hb = python_sweep(b, p, q, seed, s, Hb, delayed=delayed)
+            assert np.array_equal(a, b) and Ha == Hb, (Lx, Ly, p, q, s)
+
+
+def test_phase_order_is_exercised():
+    # Cell order agrees with the phase order except where the cell tiling
+    # wraps inside a block (cell 0's left edge meets the last cell's right
+    # column), so a difference takes some sweeps to appear: over 25 sweeps
+    # the phase-ordered transcription follows the C oracle at every sweep
+    # while the cell-ordered one departs from it.
+    seed = 2
+    lat0, H0 = inputs.rough_state(64, 64, seed=seed, mcs=2)
+    a, b, c = lat0.copy(), lat0.copy(), lat0.copy()
+    Ha = Hb = Hc = H0
+    departed = False
+    for s in range(25):
+        Ha = oracle.sweep(a, 0.8, 0.6, seed, s, Ha, delayed=True)
+        Hb = python_sweep(b, 0.8, 0.6, seed, s, Hb, delayed=True)
+        assert np.array_equal(a, b) and Ha == Hb, f"sweep {s}"
+        if not departed:
+            Hc = python_sweep(c, 0.8, 0.6, seed, s, Hc, delayed=True, phase_order=False)
+            departed = not np.array_equal(a, c)
+    assert departed
+
+
+@pytest.mark.parametrize("Lx,Ly", inputs.SHAPES_SMALL)
+def test_no_bond_twice_in_a_phase(Lx, Ly):
+    for p, q in [(1.0, 0.0), (0.5, 0.5), (0.3, 0.8)]:
+        lat = oracle.flat(Lx, Ly)
+        oracle.run(lat, p, q, 7, 0, 4, 0, check=True, delayed=True)
+
+
+@pytest.mark.parametrize("p,q", inputs.PQ_LIST)
+def test_invariants(p, q):
+    Lx, Ly = 96, 64
+    N = Lx * Ly
+    lat = oracle.flat(Lx, Ly)
+    cnt = oracle.Counts()
+    H0 = 0
+    prev = oracle.width_sums(lat, H0)[0]
+    for s in range(6):
+        H0 = oracle.sweep(lat, p, q, 11, s, H0, counts=cnt, delayed=True)
+        S1, _ = oracle.width_sums(lat, H0)
+        assert S1 - N // 2 == 2 * (cnt.att - cnt.det)
+        if q == 0.0:
+            assert S1 >= prev
+        prev = S1
+    if p == 0.0 and q == 0.0:
+        assert np.array_equal(lat, oracle.flat(Lx, Ly)) and H0 == 0
+
+
+def test_mirror_symmetry():
+    lat, H0 = inputs.rough_state(64, 96, seed=4, mcs=3)
+    a, b = lat.copy(), lat ^ 3
+    Ha, Hb = H0, -H0
+    for s in range(4):
+        Ha = oracle.sweep(a, 0.9, 0.2, 9, s, Ha, delayed=True)
+        Hb = oracle.sweep(b, 0.2, 0.9, 9, s, Hb, delayed=True)
+    assert np.array_equal(a ^ 3, b) and Ha == -Hb
+
+
+def test_delayed_differs_from_dead():
+    lat, H0 = inputs.rough_state(64, 64, seed=5, mcs=2)
+    a, b = lat.copy(), lat.copy()
+    oracle.run(a, 0.7, 0.3, 5, 0, 2, H0)
+    oracle.run(b, 0.7, 0.3, 5, 0, 2, H0, delayed=True)
+    assert not np.array_equal(a, b)
+
+
+def test_cell_side_one_is_refused():
+    blk = oracle.flat(4, 4)
+    with pytest.raises(ValueError):
+        oracle.block_sweep(blk, 1, 1, 0, 0, 1.0, 0.0, delayed=True)
+
+
+@pytest.mark.parametrize("p,q", [(1.0, 0.0), (0.5, 0.5)])
+def test_exact_4x4_law(p, q):
+    R, tmax = 40000, 10
+    ens = oracle.ensemble(4, 4, p, q, seed0=2000, R=R, tmax=tmax, delayed=True)
+    M = E.tiled_mcs_matrix(p, q, delayed=True)
+    assert np.allclose(M.sum(axis=1), 1.0, atol=1e-12)
+    laws = E.evolve(M, [1, 2, 10])
+    for t in (1, 2, 10):
+        pv = _histogram_test(ens[:, t - 1, :], E.w2_law(laws[t]))
+        assert pv > 1e-4, f"t={t}: p-value {pv}"
+    # with one cell per block both contracts attempt a uniform block-local
+    # site at every step (the cell origin is uniform), so their exact laws
+    # agree up to the rounding of the 16-bit draw over 9 active sites; the
+    # contracts part only where cells meet (the tests above)
+    Md = E.tiled_mcs_matrix(p, q)
+    assert np.abs(M - Md).max() < 1e-3
