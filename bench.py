@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=0.005,
                     help="ensemble leg: fraction of the full t = 20 L^1.6 (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving leg: jobs (0 skips it)")
+    ap.add_argument("--cell-borders", choices=("dead", "delayed"), default="dead",
+                    help="thread-cell borders of the tiled dynamics")
     ap.add_argument("--psd-calls", type=int, default=3,
                     help="spectrum of the final surface: timed calls (0 skips it)")
     args = ap.parse_args()
@@ -225,6 +227,8 @@ def main():
     stream = torch.cuda.current_stream()
     sim = okpz.okpz_init_on(L, L, p, q, seed, buf.data_ptr(), nbytes, stream.cuda_stream)
     sim.set_threads(args.threads)
+    if args.cell_borders == "delayed":
+        sim.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
 
     sim.sweep(args.warmup)
     torch.cuda.synchronize()
@@ -269,7 +273,8 @@ def main():
         "config": {"workload": f"octahedron model {L}x{L} periodic, flat init, p=1 q=0, seed 1, "
                                f"MCS {t_lo}..{t_hi}, exact W^2 at t_(i+1)=(t_i+10)e^0.01",
                    "Lx": L, "Ly": L, "p": p, "q": q, "seed": seed,
-                   "width_samples": len(widths), "threads_per_workgroup": args.threads},
+                   "width_samples": len(widths), "threads_per_workgroup": args.threads,
+                   "cell_borders": args.cell_borders},
         "sweep_kernel_ms": sweep_ms,
         "sweep_site_updates_per_s": N / (sweep_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,

@@ -125,6 +125,22 @@ int okpz_load(okpz_sim **out, const void *buf, size_t bytes);
  * (seed, sweep, block, step, cell), never by thread. */
 int okpz_set_threads(okpz_sim *s, int threads);
 
+/* Thread-cell borders of the tiled dynamics (Sec. II).
+ * OKPZ_CELLS_DEAD (the default): each 8x8 thread cell draws one of its 7x7
+ * sites off its left column and bottom row at every step, so attempts of one
+ * step never touch a common bond.
+ * OKPZ_CELLS_DELAYED: each cell draws one of all 64 sites; a step first
+ * applies the attempts on cell-bulk sites, then those on the cells' left
+ * columns and bottom rows, then those on their corners -- the paper's
+ * delayed borders, where a thread on its cell's border waits for the bulk
+ * updates and corners wait longest.  Block borders stay dead in both.
+ * Takes effect from the next sweep; a checkpoint records it.  Both variants
+ * are deterministic functions of the seed, each with its own trajectory. */
+#define OKPZ_CELLS_DEAD 0
+#define OKPZ_CELLS_DELAYED 1
+int okpz_set_cell_borders(okpz_sim *s, int32_t kind);
+int okpz_get_cell_borders(const okpz_sim *s, int32_t *kind);
+
 /* Wait for the handle's stream. */
 int okpz_sync(okpz_sim *s);
 

@@ -32,6 +32,7 @@ struct okpz_sim {
     void *mem;
     bool own_mem;
     int threads;  // sweep workgroup size (execution mapping only)
+    int32_t cell_borders;  // OKPZ_CELLS_DEAD or OKPZ_CELLS_DELAYED
     void *psd_mem;  // spectrum scratch, allocated by the first okpz_psd
 };
 
@@ -274,7 +275,7 @@ int upload_lattice(okpz_sim *s, const uint8_t *host)
 struct CkptHeader {
     char magic[8];
     uint32_t version;
-    uint32_t pad;
+    uint32_t cell_borders;  // 0 in checkpoints of dead-border runs
     int64_t Lx, Ly;
     double p, q;
     uint64_t seed;
@@ -372,6 +373,7 @@ int okpz_sweep(okpz_sim *s, int64_t n_mcs)
     const bool trivial = (s->Tp == 0 || s->Tp == (uint64_t(1) << 32)) &&
                          (s->Tq == 0 || s->Tq == (uint64_t(1) << 32));
     a.need_accept_draws = trivial ? 0 : 1;
+    a.delayed_cells = s->cell_borders == OKPZ_CELLS_DELAYED ? 1 : 0;
     for (int64_t n = 0; n < n_mcs; ++n) {
         const uint32_t sw = (uint32_t)s->t;
         int32_t sx, sy;
@@ -539,6 +541,7 @@ int okpz_save(okpz_sim *s, void *buf, size_t *bytes)
     CkptHeader h{};
     std::memcpy(h.magic, "OKPZCKP1", 8);
     h.version = 1;
+    h.cell_borders = (uint32_t)s->cell_borders;
     h.Lx = s->Lx;
     h.Ly = s->Ly;
     h.p = s->p;
@@ -562,7 +565,8 @@ int okpz_load(okpz_sim **out, const void *buf, size_t bytes)
     std::memcpy(&h, buf, sizeof h);
     if (std::memcmp(h.magic, "OKPZCKP1", 8) != 0 || h.version != 1)
         return fail(OKPZ_EINVAL, "not an okpz checkpoint");
-    if (!size_ok(h.Lx) || !size_ok(h.Ly) || h.ox < 0 || h.ox >= h.Lx || h.t < 0)
+    if (!size_ok(h.Lx) || !size_ok(h.Ly) || h.ox < 0 || h.ox >= h.Lx || h.t < 0 ||
+        h.cell_borders > OKPZ_CELLS_DELAYED)
         return fail(OKPZ_EINVAL, "corrupt checkpoint header");
     const size_t pb = plane_bytes(h.Lx, h.Ly);
     if (bytes < sizeof h + pb) return fail(OKPZ_EINVAL, "checkpoint truncated");
@@ -584,7 +588,24 @@ int okpz_load(okpz_sim **out, const void *buf, size_t bytes)
     s->cur = 0;
     s->ox = h.ox;
     s->t = h.t;
+    s->cell_borders = (int32_t)h.cell_borders;
     *out = s;
+    return OKPZ_OK;
+}
+
+int okpz_set_cell_borders(okpz_sim *s, int32_t kind)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    if (kind != OKPZ_CELLS_DEAD && kind != OKPZ_CELLS_DELAYED)
+        return fail(OKPZ_EINVAL, "cell border kind %d is neither dead (0) nor delayed (1)", kind);
+    s->cell_borders = kind;
+    return OKPZ_OK;
+}
+
+int okpz_get_cell_borders(const okpz_sim *s, int32_t *kind)
+{
+    if (!s || !kind) return fail(OKPZ_EINVAL, "null argument");
+    *kind = s->cell_borders;
     return OKPZ_OK;
 }
 

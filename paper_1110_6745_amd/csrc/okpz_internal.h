@@ -67,6 +67,7 @@ struct SweepLaunch {
     uint64_t Tp, Tq;
     int32_t blk00, u00, v00;
     int32_t need_accept_draws;
+    int32_t delayed_cells;  // 1: delayed thread-cell borders, 0: dead ones
 };
 
 // Block shift of sweep s (host side; the kernel uses the same values).

@@ -65,13 +65,20 @@ hipError_t launch_m(const SweepLaunch &a, hipStream_t st)
     return launch_b<kThreads, kMode, 0>(a, st);
 }
 
+template <int kThreads, int kCells>
+hipError_t launch_c(const SweepLaunch &a, hipStream_t st)
+{
+    const uint64_t one = uint64_t(1) << 32;
+    if (a.need_accept_draws) return launch_m<kThreads, kDraw | kCells>(a, st);
+    if (a.Tp == one && a.Tq == 0) return launch_m<kThreads, kGrowth | kCells>(a, st);
+    return launch_m<kThreads, kFixed | kCells>(a, st);
+}
+
 template <int kThreads>
 hipError_t launch_t(const SweepLaunch &a, hipStream_t st)
 {
-    const uint64_t one = uint64_t(1) << 32;
-    if (a.need_accept_draws) return launch_m<kThreads, kDraw>(a, st);
-    if (a.Tp == one && a.Tq == 0) return launch_m<kThreads, kGrowth>(a, st);
-    return launch_m<kThreads, kFixed>(a, st);
+    if (a.delayed_cells) return launch_c<kThreads, core::kDelayedCells>(a, st);
+    return launch_c<kThreads, 0>(a, st);
 }
 
 }  // namespace

@@ -49,8 +49,12 @@ constexpr int kMaxGroup = 64;                          // blocks per group (32 x
 constexpr int kGroupLds = 65536 + kMaxGroup * 32 + kMaxGroup * 32 * 4 + kMaxGroup * 3 * 4;
 
 // Acceptance modes: p = 1, q = 0 (pure growth); p and q each 0 or 1;
-// general p, q (per-attempt acceptance draws).
-enum Mode : int { kGrowth = 0, kFixed = 1, kDraw = 2 };
+// general p, q (per-attempt acceptance draws).  kDelayedCells added to a
+// mode selects the delayed thread-cell borders of Sec. II: every cell draws
+// one of its 64 sites, and a step applies the attempts on cell-bulk sites,
+// then those on cell edges, then those on cell corners, with a barrier
+// after each phase.
+enum Mode : int { kGrowth = 0, kFixed = 1, kDraw = 2, kDelayedCells = 4 };
 
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
 {
@@ -129,10 +133,45 @@ __host__ __device__ inline int group_size(int Bx, int By, int nblk)
 //   kFixedB = 0:   any block sides 32..256, geometry from `a`.
 // smem: at least G * (By + 1) * Bx bytes; opk: G * 35 words of LDS (origins,
 // then the blocks' placement when kFixedB = 0).
-template <int kThreads, int kMode, int kFixedB>
+// Eq. (1) on the five-bit code of a site byte s, its left neighbour's byte l
+// and its lower neighbour's byte d; r is the attempt's acceptance draw
+// (kDraw only).
+template <int kMode>
+__device__ __forceinline__ bool move_accepted(uint32_t sv, uint32_t lv, uint32_t dv,
+                                              uint32_t fixed_tbl, uint32_t r, uint64_t Tp,
+                                              uint64_t Tq)
+{
+    if (kMode == kGrowth) {
+        // minimum: s == 0 (nx = ny = 0 and copies, not dead), l & 8 (nx of
+        // the left bond) and d & 16 (ny of the lower bond) set:
+        // (~l & 8) | (~d & 16) | s == 0, two bit operations (truth table
+        // 0xAE: (~A & B) | C)
+        const uint32_t t = __builtin_amdgcn_bitop3_b32(lv, 8u, sv, 0xAE);
+        return __builtin_amdgcn_bitop3_b32(dv, 16u, t, 0xAE) == 0u;
+    }
+    // bitwise mux c ? a : b (truth table 0xE4): bit 3 from l, bit 4 from d,
+    // the others from s
+    const uint32_t t = __builtin_amdgcn_bitop3_b32(lv, dv, 8u, 0xE4);
+    const uint32_t code = __builtin_amdgcn_bitop3_b32(t, sv, 24u, 0xE4);
+    uint32_t tbl = fixed_tbl;
+    if (kMode == kDraw)
+        tbl = ((uint64_t)r < Tp ? (1u << 24) : 0u) | ((uint64_t)r < Tq ? (1u << 3) : 0u);
+    return (tbl >> code) & 1u;
+}
+
+// LDS atomic XOR of one byte (a 32-bit atomic on the byte's word).
+__device__ __forceinline__ void xor_byte(uint8_t *smem, uint32_t off, uint32_t v)
+{
+    uint32_t *w = reinterpret_cast<uint32_t *>(smem + (off & ~3u));
+    atomicXor(w, v << (8 * (off & 3u)));
+}
+
+template <int kThreads, int kModeFull, int kFixedB>
 __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const int G,
                                             uint8_t *__restrict__ smem, uint32_t *opk)
 {
+    constexpr int kMode = kModeFull & 3;
+    constexpr bool kDelayed = (kModeFull & kDelayedCells) != 0;
     constexpr bool kDrawAccept = (kMode == kDraw);
     constexpr int kCpt = kCellsMax / kThreads;
     if (kFixedB) {
@@ -248,8 +287,9 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         const bool live = g < G;
         cid[j] = (uint32_t)c;
         bidj[j] = (uint32_t)(b0 + (live ? g : 0));
-        cxo[j] = (uint32_t)((c % ncx) * 8 + 1);
-        cyo[j] = (uint32_t)((c / ncx) * 8 + 1);
+        // dead cell borders: the active sites start one in from the origin
+        cxo[j] = (uint32_t)((c % ncx) * 8 + (kDelayed ? 0 : 1));
+        cyo[j] = (uint32_t)((c / ncx) * 8 + (kDelayed ? 0 : 1));
         mxj[j] = live ? (uint32_t)Bx - 1u : 0u;
         myj[j] = live ? (uint32_t)By - 1u : 0u;
         gbase[j] = live ? (uint32_t)(g * tsz) : 0u;
@@ -296,7 +336,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             // For a site byte that is neither 0 nor 0x1B the low three bits
             // of the site byte already rule out a move, whatever the
             // neighbour bytes hold.
-            uint32_t off[kCpt], sv[kCpt];
+            uint32_t off[kCpt], sv[kCpt], phs[kCpt];
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
                 if ((e & 1) == 0) {
@@ -308,6 +348,17 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                 const uint32_t op = opv[j] >> (6 * (e & 1));
                 const uint32_t ox = op & 7u, oy = (op >> 3) & 7u;
                 const uint32_t h16 = (e & 1) ? (sw[j][e >> 1] >> 16) : (sw[j][e >> 1] & 0xffffu);
+                if (kDelayed) {
+                    // site i = floor(64 h / 2^16) of the 8 x 8 cell: a = i mod 8,
+                    // b = i div 8; phase 0 bulk, 1 edge (one of a, b zero),
+                    // 2 corner
+                    const uint32_t ca = (h16 >> 10) & 7u, cb = h16 >> 13;
+                    phs[j] = (uint32_t)(ca == 0u) + (uint32_t)(cb == 0u);
+                    const uint32_t ur = ox + cxo[j] + ca, vr = oy + cyo[j] + cb;
+                    off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
+                    sv[j] = smem[off[j] + Bx];  // current for the bulk phase only
+                    continue;
+                }
                 // Active site i = floor(49 h / 2^16) of the 7 x 7 (row-major),
                 // split as i = 7 q + a without a division: with 7 h = q 2^16 + r,
                 // q = floor(7 h / 2^16) = i div 7 and a = floor(7 r / 2^16) = i mod 7.
@@ -345,6 +396,39 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                     asm volatile("" : "+v"(nxt[j].x), "+v"(nxt[j].y), "+v"(nxt[j].z), "+v"(nxt[j].w));
                 }
             }
+            if (kDelayed) {
+                // Three phases.  Within one, attempted sites are never nearest
+                // neighbours.  Bulk sites are not diagonal neighbours either
+                // (as in the dead-border steps), and corners are 8 apart, so
+                // plain byte stores suffice there; an edge site and the edge
+                // site diagonally up and to the left of it (the next cell's
+                // bottom row) can share a neighbour byte, so edge flips are
+                // atomic XORs.  The bulk phase uses the site byte read above.
+#pragma unroll
+                for (int ph = 0; ph < 3; ++ph) {
+#pragma unroll
+                    for (int j = 0; j < kCpt; ++j) {
+                        if (phs[j] != (uint32_t)ph) continue;
+                        const uint32_t s0 = ph == 0 ? sv[j] : (uint32_t)smem[off[j] + Bx];
+                        if (s0 != 0u && (kMode == kGrowth || s0 != 0x1Bu)) continue;
+                        const uint32_t l0 = smem[off[j] + Bx - 1];
+                        const uint32_t d0 = smem[off[j]];
+                        const uint32_t r = kDrawAccept ? aw[j][e & 3] : 0u;
+                        if (!move_accepted<kMode>(s0, l0, d0, fixed_tbl, r, a.Tp, a.Tq)) continue;
+                        if (ph == 1) {
+                            xor_byte(smem, off[j] + Bx, 0x1Bu);
+                            xor_byte(smem, off[j] + Bx - 1, 0x09u);
+                            xor_byte(smem, off[j], 0x12u);
+                        } else {
+                            smem[off[j] + Bx] = (uint8_t)(s0 ^ 0x1Bu);
+                            smem[off[j] + Bx - 1] = (uint8_t)(l0 ^ 0x09u);
+                            smem[off[j]] = (uint8_t)(d0 ^ 0x12u);
+                        }
+                    }
+                    __syncthreads();
+                }
+                continue;
+            }
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
                 // the loads zero-extend; keep the code generator from
@@ -362,28 +446,8 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             }
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
-                bool flip;
-                if (kMode == kGrowth) {
-                    // minimum: s == 0 (nx = ny = 0 and copies, not dead),
-                    // l & 8 (nx of the left bond) and d & 16 (ny of the lower
-                    // bond) set: (~l & 8) | (~d & 16) | s == 0, two bit
-                    // operations (truth table 0xAE: (~A & B) | C)
-                    const uint32_t t = __builtin_amdgcn_bitop3_b32(lv[j], 8u, sv[j], 0xAE);
-                    flip = (__builtin_amdgcn_bitop3_b32(dv[j], 16u, t, 0xAE) == 0u);
-                } else {
-                    // bitwise mux c ? a : b (truth table 0xE4): bit 3 from l,
-                    // bit 4 from d, the others from s
-                    const uint32_t t = __builtin_amdgcn_bitop3_b32(lv[j], dv[j], 8u, 0xE4);
-                    const uint32_t code = __builtin_amdgcn_bitop3_b32(t, sv[j], 24u, 0xE4);
-                    uint32_t tbl = fixed_tbl;
-                    if (kDrawAccept) {
-                        const uint32_t r = aw[j][e & 3];
-                        tbl = ((uint64_t)r < a.Tp ? (1u << 24) : 0u) |
-                              ((uint64_t)r < a.Tq ? (1u << 3) : 0u);
-                    }
-                    flip = (tbl >> code) & 1u;
-                }
-                if (flip) {
+                const uint32_t r = kDrawAccept ? aw[j][e & 3] : 0u;
+                if (move_accepted<kMode>(sv[j], lv[j], dv[j], fixed_tbl, r, a.Tp, a.Tq)) {
                     // a growth flip only ever turns 0 (minimum) into 0x1B
                     smem[off[j] + Bx] = (kMode == kGrowth) ? (uint8_t)0x1Bu : (uint8_t)(sv[j] ^ 0x1Bu);
                     smem[off[j] + Bx - 1] = (uint8_t)(lv[j] ^ 0x09u);

@@ -25,6 +25,8 @@ OKPZ_ENOMEM = -12
 OKPZ_EOVERFLOW = -75
 OKPZ_EDEVICE = -5
 OKPZ_EBUSY = -16
+OKPZ_CELLS_DEAD = 0
+OKPZ_CELLS_DELAYED = 1
 
 
 class OkpzError(RuntimeError):
@@ -72,6 +74,8 @@ _sig("okpz_set_lattice", ctypes.c_int, _vp, _u8p, _sz, _i64, _i64)
 _sig("okpz_save", ctypes.c_int, _vp, _vp, ctypes.POINTER(_sz))
 _sig("okpz_load", ctypes.c_int, ctypes.POINTER(_vp), _vp, _sz)
 _sig("okpz_set_threads", ctypes.c_int, _vp, ctypes.c_int)
+_sig("okpz_set_cell_borders", ctypes.c_int, _vp, ctypes.c_int32)
+_sig("okpz_get_cell_borders", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int32))
 _sig("okpz_sync", ctypes.c_int, _vp)
 _sig("okpz_free", ctypes.c_int, _vp)
 _sig("okpz_last_error", ctypes.c_char_p)
@@ -118,7 +122,8 @@ _sig("okpz_serve_free", ctypes.c_int, _vp)
 
 EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on", "okpz_sweep",
             "okpz_width", "okpz_w2", "okpz_psd", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
-            "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads", "okpz_sync",
+            "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads",
+            "okpz_set_cell_borders", "okpz_get_cell_borders", "okpz_sync",
             "okpz_free", "okpz_last_error", "okpz_batch_create", "okpz_batch_set_mapping",
             "okpz_batch_get_mapping", "okpz_batch_autotune", "okpz_batch_run",
             "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
@@ -256,6 +261,15 @@ class Sim:
 
     def set_threads(self, threads: int) -> None:
         _check(_lib.okpz_set_threads(self._h, int(threads)))
+
+    def set_cell_borders(self, kind: int) -> None:
+        """OKPZ_CELLS_DEAD (default) or OKPZ_CELLS_DELAYED (Sec. II)."""
+        _check(_lib.okpz_set_cell_borders(self._h, int(kind)))
+
+    def cell_borders(self) -> int:
+        k = ctypes.c_int32()
+        _check(_lib.okpz_get_cell_borders(self._h, ctypes.byref(k)))
+        return k.value
 
     def sync(self) -> None:
         _check(_lib.okpz_sync(self._h))

@@ -1,0 +1,173 @@
+"""GPU parity of the delayed thread-cell borders (Sec. II) against the
+oracle, bit for bit: lattice, H0 and the exact width sums, for ragged sizes,
+every acceptance regime, rough starts at large sweep indices, every
+workgroup size, a hundred consecutive sweeps, checkpoints, and the
+benchmark's 2^17 x 2^17 launch configuration on sampled blocks."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import inputs
+from tests.test_gpu_fullsize import flat_block
+from tests.test_gpu_parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def okpz():
+    from paper_1110_6745_amd import okpz as m
+
+    return m
+
+
+def delayed_sim(okpz, Lx, Ly, p, q, seed, threads=1024):
+    sim = okpz.okpz_init(Lx, Ly, p, q, seed)
+    sim.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
+    sim.set_threads(threads)
+    assert sim.cell_borders() == okpz.OKPZ_CELLS_DELAYED
+    return sim
+
+
+@pytest.mark.parametrize("Lx,Ly", inputs.SHAPES_GPU)
+@pytest.mark.parametrize("p,q", [inputs.PQ_GROWTH, inputs.PQ_ASYM, (0.0, 1.0), (0.3, 0.8)])
+def test_sweeps_match_oracle(okpz, Lx, Ly, p, q):
+    seed = 7
+    sim = delayed_sim(okpz, Lx, Ly, p, q, seed)
+    lat, H0 = oracle.flat(Lx, Ly), 0
+    for s in range(3):
+        sim.sweep(1)
+        H0 = oracle.sweep(lat, p, q, seed, s, H0, delayed=True)
+        compare(sim, lat, H0, f"delayed {Lx}x{Ly} p={p} q={q} after sweep {s}")
+    sim.free()
+
+
+@pytest.mark.parametrize("Lx,Ly,seed", [(64, 96, 3), (256, 256, 2**40 + 17), (512, 1024, 5)])
+def test_rough_start_and_large_indices(okpz, Lx, Ly, seed):
+    lat, H0 = inputs.rough_state(Lx, Ly, seed=seed % 1000, mcs=4)
+    t0 = 2**31 + 11
+    for p, q in [(0.95, 0.05), (0.5, 0.5)]:
+        sim = delayed_sim(okpz, Lx, Ly, p, q, seed)
+        sim.set_lattice(lat, H0, t0)
+        ref, Hr = lat.copy(), H0
+        for s in range(t0, t0 + 3):
+            sim.sweep(1)
+            Hr = oracle.sweep(ref, p, q, seed, s, Hr, delayed=True)
+        compare(sim, ref, Hr, f"delayed rough {Lx}x{Ly} p={p}")
+        sim.free()
+
+
+@pytest.mark.parametrize("Lx,Ly", [(256, 256), (96, 64), (1056, 96)])
+def test_every_workgroup_size_gives_the_same_bits(okpz, Lx, Ly):
+    ref = oracle.flat(Lx, Ly)
+    H0 = oracle.run(ref, 0.95, 0.05, 6, 0, 4, 0, delayed=True)
+    for threads in (256, 512, 1024):
+        sim = delayed_sim(okpz, Lx, Ly, 0.95, 0.05, 6, threads)
+        sim.sweep(4)
+        compare(sim, ref, H0, f"delayed threads={threads}")
+        sim.free()
+
+
+@pytest.mark.parametrize("p,q", [inputs.PQ_GROWTH, inputs.PQ_ASYM])
+def test_a_hundred_sweeps(okpz, p, q):
+    L = 256
+    sim = delayed_sim(okpz, L, L, p, q, 1)
+    lat, H0 = oracle.flat(L, L), 0
+    for s in range(100):
+        sim.sweep(1)
+        H0 = oracle.sweep(lat, p, q, 1, s, H0, delayed=True)
+        assert sim.h0() == H0, f"sweep {s}"
+        if s % 20 == 19:
+            assert np.array_equal(sim.get_lattice(), lat), f"sweep {s}"
+    sim.free()
+
+
+def test_switching_and_checkpoint(okpz):
+    L, seed = 128, 9
+    sim = okpz.okpz_init(L, L, 0.9, 0.1, seed)
+    lat, H0 = oracle.flat(L, L), 0
+    sim.sweep(2)
+    H0 = oracle.run(lat, 0.9, 0.1, seed, 0, 2, H0)
+    sim.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
+    sim.sweep(2)
+    H0 = oracle.run(lat, 0.9, 0.1, seed, 2, 2, H0, delayed=True)
+    compare(sim, lat, H0, "dead then delayed")
+    ck = sim.save()
+    back = okpz.okpz_load(ck)
+    assert back.cell_borders() == okpz.OKPZ_CELLS_DELAYED
+    back.sweep(2)
+    H0 = oracle.run(lat, 0.9, 0.1, seed, 4, 2, H0, delayed=True)
+    compare(back, lat, H0, "restored delayed run")
+    back.set_cell_borders(okpz.OKPZ_CELLS_DEAD)
+    back.sweep(1)
+    H0 = oracle.run(lat, 0.9, 0.1, seed, 6, 1, H0)
+    compare(back, lat, H0, "delayed then dead")
+    with pytest.raises(okpz.OkpzError) as e:
+        back.set_cell_borders(2)
+    assert e.value.code == okpz.OKPZ_EINVAL
+    sim.free()
+    back.free()
+
+
+def test_full_size_one_sweep_on_sampled_blocks(okpz):
+    L = 1 << 17
+    seed, p, q = 1, 1.0, 0.0
+    sim = delayed_sim(okpz, L, L, p, q, seed)
+    sim.sweep(1)
+    Bx, By, C = oracle.geometry(L, L)
+    nbx = L // Bx
+    sx, sy = oracle.block_shift(seed, 0, Bx, By)
+    i00, u00 = ((L - sx) % L) // Bx, ((L - sx) % L) % Bx
+    j00, v00 = ((L - sy) % L) // By, ((L - sy) % L) % By
+    rng = np.random.default_rng(11)
+    rows_j = sorted({0, j00, nbx - 1, *rng.integers(0, nbx, 2).tolist()})
+    cols_i = sorted({0, i00, nbx - 1, *rng.integers(0, nbx, 2).tolist()})
+    dh_total = 0
+    for j in rows_j:
+        y0 = (sy + j * By) % L
+        got_rows = sim.get_rows(y0, By)
+        for i in cols_i:
+            x0 = (sx + i * Bx) % L
+            blk = flat_block(x0, y0, Bx, By)
+            site00 = (u00, v00) if (i == i00 and j == j00) else (-1, -1)
+            dh, _, _ = oracle.block_sweep(blk, C, seed, 0, j * nbx + i, p, q, site00, delayed=True)
+            dh_total += dh
+            xs = (x0 + np.arange(Bx)) % L
+            assert np.array_equal(got_rows[:, xs], blk), f"block ({i},{j}) differs"
+        print(f"block row {j} ok", flush=True)
+    assert sim.h0() == dh_total
+    sim.free()
+
+
+def test_growth_width_against_random_sequential(okpz):
+    """Sec. II expects the decomposition to change prefactors at most, not
+    exponents: the excess width W^2 - 1/4 of both border contracts (GPU) and
+    of the random-sequential judge (oracle) during growth, averaged over
+    seeds, agree within their statistical errors.  Prints the table."""
+    L, R, p, q = 256, 12, 1.0, 0.0
+    times = [10, 30, 100, 200]
+    N = L * L
+
+    def excess(S1S2):
+        S1, S2 = S1S2[..., 0].astype(object), S1S2[..., 1].astype(object)
+        return np.array((N * S2 - S1 * S1) / (N * N), dtype=float) - 0.25
+
+    rsu = oracle.ensemble(L, L, p, q, seed0=500, R=R, tmax=max(times), rsu=True)
+    rows = {"rsu": np.array([excess(rsu[:, t - 1, :]) for t in times]).T}
+    for kind, name in ((okpz.OKPZ_CELLS_DEAD, "dead"), (okpz.OKPZ_CELLS_DELAYED, "delayed")):
+        w = np.zeros((R, len(times)))
+        for r in range(R):
+            sim = okpz.okpz_init(L, L, p, q, 500 + r)
+            sim.set_cell_borders(kind)
+            for i, t in enumerate(times):
+                w[r, i] = excess(np.array(sim.width(t), dtype=np.int64))
+            sim.free()
+        rows[name] = w
+    print(f"\nexcess W^2, L={L}, {R} seeds: t " + " ".join(f"{t:>8d}" for t in times))
+    for name, w in rows.items():
+        print(f"{name:>8s}: " + " ".join(f"{m:8.4f}" for m in w.mean(axis=0)))
+    for name in ("dead", "delayed"):
+        d = rows[name].mean(axis=0) - rows["rsu"].mean(axis=0)
+        err = np.sqrt(rows[name].var(axis=0, ddof=1) / R + rows["rsu"].var(axis=0, ddof=1) / R)
+        print(f"{name:>8s} - rsu in standard errors: " + " ".join(f"{v:6.2f}" for v in d / err))
+        assert np.all(np.abs(d) < 5 * err + 0.02 * rows["rsu"].mean(axis=0)), name
