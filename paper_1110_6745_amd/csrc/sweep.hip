@@ -10,8 +10,13 @@ using core::kDraw;
 using core::kFixed;
 using core::kGrowth;
 
+// Groups per launch: a grid dimension holds fewer than 2^32 work-items, so
+// the sweep of a lattice above 2^18 x 2^18 sites takes several launches
+// (blocks are independent within a sweep; the order does not matter).
+constexpr int kMaxGroupsPerLaunch = 1 << 21;
+
 template <int kThreads, int kMode, int kFixedB>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a, int G)
+__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a, int G, int g0)
 {
     // 256 x 256 blocks use a static tile (its base folds into the LDS
     // instruction offsets); other block sides use dynamic LDS.
@@ -19,12 +24,13 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a, int G)
     __shared__ __align__(16) uint8_t smem_fix[kFixedB ? (kFixedB + 1) * kFixedB : 16];
     __shared__ uint32_t opk_fix[kFixedB ? 32 : 1];
     const int nblk = a.nbx * a.nby;
-    const int ngroups = (nblk + G - 1) / G;
+    const int nl = gridDim.x;  // groups of this launch, starting at group g0
     // XCD-aware order: consecutive workgroups are dealt round-robin to the 8
     // XCDs; give each XCD a contiguous run of groups so neighbouring blocks
     // (which read overlapping words) share that XCD's L2.
     int gid = blockIdx.x;
-    if ((ngroups & 7) == 0) gid = (blockIdx.x & 7) * (ngroups >> 3) + (blockIdx.x >> 3);
+    if ((nl & 7) == 0) gid = (blockIdx.x & 7) * (nl >> 3) + (blockIdx.x >> 3);
+    gid += g0;
     const int b0 = gid * G;
     const int Gc = min(G, nblk - b0);
     if (kFixedB) {
@@ -53,8 +59,11 @@ hipError_t launch_b(const SweepLaunch &a, hipStream_t st)
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((sweep_kernel<kThreads, kMode, kFixedB>), dim3(ngroups), dim3(kThreads), lds,
-                       st, a, G);
+    for (int g0 = 0; g0 < ngroups; g0 += kMaxGroupsPerLaunch) {
+        const int n = ngroups - g0 < kMaxGroupsPerLaunch ? ngroups - g0 : kMaxGroupsPerLaunch;
+        hipLaunchKernelGGL((sweep_kernel<kThreads, kMode, kFixedB>), dim3(n), dim3(kThreads), lds, st,
+                           a, G, g0);
+    }
     return hipGetLastError();
 }
 

@@ -97,3 +97,35 @@ def test_full_length_rows_and_columns(okpz, Lx, Ly):
     assert sim.width() == oracle.width_sums(lat, H1)
     assert np.array_equal(sim.get_lattice(), lat) and sim.h0() == H1
     sim.free()
+
+
+def test_sweep_split_over_launches_at_2_19(okpz):
+    # 2^19 x 2^19 (128 GiB for both copies) has 2^22 blocks of 256^2, more
+    # work-items than one grid dimension holds: the sweep runs as two
+    # launches; sampled blocks of both halves and H0 match the oracle
+    L = 1 << 19
+    seed, p, q = 3, 1.0, 0.0
+    sim = okpz.okpz_init(L, L, p, q, seed)
+    sim.sweep(1)
+    Bx, By, C = oracle.geometry(L, L)
+    nbx = L // Bx
+    sx, sy = oracle.block_shift(seed, 0, Bx, By)
+    i00, u00 = ((L - sx) % L) // Bx, ((L - sx) % L) % Bx
+    j00, v00 = ((L - sy) % L) // By, ((L - sy) % L) % By
+    rows_j = sorted({0, j00, nbx // 2 - 1, nbx // 2, nbx - 1})
+    cols_i = sorted({0, i00, 7, nbx - 1})
+    dh_total = 0
+    for j in rows_j:
+        y0 = (sy + j * By) % L
+        got_rows = sim.get_rows(y0, By)
+        for i in cols_i:
+            x0 = (sx + i * Bx) % L
+            blk = flat_block(x0, y0, Bx, By)
+            site00 = (u00, v00) if (i == i00 and j == j00) else (-1, -1)
+            dh, _, _ = oracle.block_sweep(blk, C, seed, 0, j * nbx + i, p, q, site00)
+            dh_total += dh
+            xs = (x0 + np.arange(Bx)) % L
+            assert np.array_equal(got_rows[:, xs], blk), f"block ({i},{j}) differs"
+        print(f"block row {j} ok", flush=True)
+    assert sim.h0() == dh_total
+    sim.free()
