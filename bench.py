@@ -63,10 +63,25 @@ def cpu_baseline(budget_s=12.0):
         el = time.perf_counter() - t0
         if el >= budget_s or s >= 400:
             break
+    # one core, the paper's non-parallel reference point (Sec. III)
+    oracle.set_num_threads(1)
+    try:
+        lat1 = oracle.flat(L, L)
+        H1, s1, t1 = 0, 0, time.perf_counter()
+        while True:
+            H1 = oracle.sweep(lat1, 1.0, 0.0, 1, s1, H1)
+            s1 += 1
+            el1 = time.perf_counter() - t1
+            if el1 >= budget_s / 3 or s1 >= 100:
+                break
+    finally:
+        oracle.set_num_threads(threads)
     return {"value": L * L * s / el, "unit": "site updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{s} MCS of a 4096x4096 flat lattice (p=1, q=0, seed 1; 256 blocks of the "
-                      f"2^17 workload's 256x256 geometry), {el:.1f} s, OpenMP over blocks"}
+                      f"2^17 workload's 256x256 geometry), {el:.1f} s, OpenMP over blocks",
+            "single_core": {"value": L * L * s1 / el1, "cores": 1,
+                            "sample": f"{s1} MCS of the same lattice, {el1:.1f} s"}}
 
 
 def ensemble_jobs(scale):

@@ -179,6 +179,13 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
 int okpz_batch_set_mapping(okpz_batch *b, int32_t threads, int32_t workgroups);
 int okpz_batch_get_mapping(okpz_batch *b, int32_t *threads, int32_t *workgroups);
 
+/* Thread-cell borders of every job of the batch (OKPZ_CELLS_DEAD, the
+ * default, or OKPZ_CELLS_DELAYED; see okpz_set_cell_borders).  Applies from
+ * the next okpz_batch_run or okpz_batch_autotune; each job's trajectory is the
+ * one okpz_sweep gives a lone lattice with the same borders. */
+int okpz_batch_set_cell_borders(okpz_batch *b, int32_t kind);
+int okpz_batch_get_cell_borders(const okpz_batch *b, int32_t *kind);
+
 /* Pick the mapping by timing every candidate on a scaled-down copy of the
  * workload: the longest job runs trial_mcs sweeps and every other job the
  * same fraction of its own t_max (at least one sweep); results are

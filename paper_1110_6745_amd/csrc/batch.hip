@@ -181,7 +181,9 @@ __device__ int find_and_claim(uint64_t *claim, const int32_t *nitems, const int3
     return -1;
 }
 
-template <int kThreads>
+// kCells: 0 for dead thread-cell borders, core::kDelayedCells for delayed
+// ones (one kind per launch).
+template <int kThreads, int kCells>
 __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const JobDesc *jobs, JobState *state,
                                                          Control *ctl, uint64_t *claim,
                                                          const int32_t *sched, int32_t njobs,
@@ -245,11 +247,11 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
             const int b0 = gi * jd.G;
             const int Gc = min(jd.G, jd.nbx * jd.nby - b0);
             if (jd.mode == core::kGrowth)
-                run_group<kThreads, core::kGrowth>(a, b0, Gc, smem);
+                run_group<kThreads, core::kGrowth | kCells>(a, b0, Gc, smem);
             else if (jd.mode == core::kFixed)
-                run_group<kThreads, core::kFixed>(a, b0, Gc, smem);
+                run_group<kThreads, core::kFixed | kCells>(a, b0, Gc, smem);
             else
-                run_group<kThreads, core::kDraw>(a, b0, Gc, smem);
+                run_group<kThreads, core::kDraw | kCells>(a, b0, Gc, smem);
             __syncthreads();  // the group's tile is reused by the next group
         }
 
@@ -367,6 +369,7 @@ struct okpz_batch {
     hipStream_t stream = nullptr;
     bool ran = false;
     float last_ms = 0.f;
+    int32_t cell_borders = OKPZ_CELLS_DEAD;
 };
 
 namespace {
@@ -477,14 +480,15 @@ struct Ring {
     int32_t *sched;  // items per sweep, then scan order
     int njobs;
     hipStream_t stream;
+    int delayed_cells;  // 1: delayed thread-cell borders
 };
 
-template <int kThreads>
+template <int kThreads, int kCells>
 hipError_t launch_ring(const Ring &R, int wgs)
 {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)okpz::batch::batch_kernel<kThreads>,
+        hipError_t e = hipFuncSetAttribute((const void *)okpz::batch::batch_kernel<kThreads, kCells>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            okpz::core::kGroupLds);
         if (e != hipSuccess) return e;
@@ -493,19 +497,26 @@ hipError_t launch_ring(const Ring &R, int wgs)
     // about 2 s without any group completing anywhere (one probe: a scan of
     // the claim words plus a sleep of 16 x 64 cycles)
     const uint64_t idle_limit = 1ull << 19;
-    hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads>), dim3(wgs), dim3(kThreads),
+    hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells>), dim3(wgs), dim3(kThreads),
                        okpz::core::kGroupLds, R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
                        (int32_t)R.njobs, idle_limit);
     return hipGetLastError();
 }
 
-hipError_t launch_any(const Ring &R, int threads, int wgs)
+template <int kCells>
+hipError_t launch_cells(const Ring &R, int threads, int wgs)
 {
     switch (threads) {
-    case 256: return launch_ring<256>(R, wgs);
-    case 512: return launch_ring<512>(R, wgs);
-    default: return launch_ring<1024>(R, wgs);
+    case 256: return launch_ring<256, kCells>(R, wgs);
+    case 512: return launch_ring<512, kCells>(R, wgs);
+    default: return launch_ring<1024, kCells>(R, wgs);
     }
+}
+
+hipError_t launch_any(const Ring &R, int threads, int wgs)
+{
+    if (R.delayed_cells) return launch_cells<okpz::core::kDelayedCells>(R, threads, wgs);
+    return launch_cells<0>(R, threads, wgs);
 }
 
 // After a launch: OKPZ_OK if every job reached its stop target.
@@ -523,7 +534,8 @@ int check_control(const Ring &R)
 
 Ring ring_of(okpz_batch *b)
 {
-    return Ring{b->d_desc, b->d_state, b->d_ctl, b->d_claim, b->d_sched, (int)b->jobs.size(), b->stream};
+    return Ring{b->d_desc, b->d_state, b->d_ctl, b->d_claim, b->d_sched, (int)b->jobs.size(), b->stream,
+                b->cell_borders == OKPZ_CELLS_DELAYED ? 1 : 0};
 }
 
 int run(okpz_batch *b, int threads, int wgs, float *ms)
@@ -667,6 +679,22 @@ int okpz_batch_set_mapping(okpz_batch *b, int32_t threads, int32_t workgroups)
     if (workgroups < 0 || workgroups > (1 << 16)) return bfail(OKPZ_EINVAL, "workgroups out of range");
     b->threads = threads;
     b->workgroups = workgroups;
+    return OKPZ_OK;
+}
+
+int okpz_batch_set_cell_borders(okpz_batch *b, int32_t kind)
+{
+    if (!b) return bfail(OKPZ_EINVAL, "null handle");
+    if (kind != OKPZ_CELLS_DEAD && kind != OKPZ_CELLS_DELAYED)
+        return bfail(OKPZ_EINVAL, "cell border kind %d is neither dead (0) nor delayed (1)", kind);
+    b->cell_borders = kind;
+    return OKPZ_OK;
+}
+
+int okpz_batch_get_cell_borders(const okpz_batch *b, int32_t *kind)
+{
+    if (!b || !kind) return bfail(OKPZ_EINVAL, "null argument");
+    *kind = b->cell_borders;
     return OKPZ_OK;
 }
 
@@ -1345,7 +1373,7 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
     BHIP(hipEventCreate(&eg));
     BHIP(hipEventRecord(e0, sv->stream));
     const Ring R{sv->d_desc, sv->d_state, sv->d_ctl, sv->d_claim, sv->d_sched, sv->max_slots,
-                 sv->stream};
+                 sv->stream, 0};
     if (n_small > 0) {
         Control ctl{};
         ctl.finished = finished;

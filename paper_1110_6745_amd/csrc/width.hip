@@ -8,7 +8,9 @@
 //   sum_b-rows (Lx G^2 + 2 G p1 + p2)     = n_b Lx G_b^2 + 2 G_b A_b + B_b,
 // with A_b = sum (Lx g + p1), B_b = sum (Lx g^2 + 2 g p1 + p2).  Every block
 // writes (delta_b, A_b, B_b) with delta_b its sigma_y sum; one workgroup scans
-// the delta_b into G_b and adds the blocks up.
+// the delta_b into G_b and adds the blocks up.  Up to kOneGroupRows rows one
+// workgroup combines the rows directly (one launch less, which is what a
+// small lattice's measurement costs).
 #include "width_core.h"
 
 namespace okpz {
@@ -17,6 +19,7 @@ namespace {
 constexpr int kRowThreads = 256;
 constexpr int kBlockRows = 256;
 constexpr int kTotalThreads = 1024;
+constexpr int kOneGroupRows = 8192;
 
 __global__ __launch_bounds__(kRowThreads) void width_rows_kernel(LatticeView v, int64_t *rows)
 {
@@ -26,6 +29,13 @@ __global__ __launch_bounds__(kRowThreads) void width_rows_kernel(LatticeView v, 
     const int y = blockIdx.x * (kRowThreads / 64) + (threadIdx.x >> 6);
     if (y >= v.Ly) return;
     core::width_row(v, y, threadIdx.x & 63, lut, rows);
+}
+
+__global__ __launch_bounds__(kTotalThreads) void width_final_kernel(const int64_t *rows, int32_t Lx,
+                                                                    int32_t Ly, int64_t *out)
+{
+    __shared__ int64_t lds[64];
+    core::width_combine(rows, Lx, Ly, out, lds);
 }
 
 // blk[4 b ..] = {delta_b, A_b, B_b lo, B_b hi} of rows [b kBlockRows, ...).
@@ -102,6 +112,11 @@ hipError_t launch_width(const LatticeView &v, int64_t *rows, int64_t *out, hipSt
 {
     const hipError_t e = launch_width_rows(v, rows, st);
     if (e != hipSuccess) return e;
+    if (v.Ly <= kOneGroupRows) {
+        hipLaunchKernelGGL(width_final_kernel, dim3(1), dim3(kTotalThreads), 0, st, rows, v.Lx, v.Ly,
+                           out);
+        return hipGetLastError();
+    }
     const int32_t nb = width_blocks(v.Ly);
     int64_t *blk = rows + 3 * (size_t)v.Ly;
     hipLaunchKernelGGL(width_blocks_kernel, dim3(nb), dim3(kBlockRows), 0, st, rows, v.Lx, v.Ly,

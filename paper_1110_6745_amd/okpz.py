@@ -75,6 +75,8 @@ _sig("okpz_save", ctypes.c_int, _vp, _vp, ctypes.POINTER(_sz))
 _sig("okpz_load", ctypes.c_int, ctypes.POINTER(_vp), _vp, _sz)
 _sig("okpz_set_threads", ctypes.c_int, _vp, ctypes.c_int)
 _sig("okpz_set_cell_borders", ctypes.c_int, _vp, ctypes.c_int32)
+_sig("okpz_batch_set_cell_borders", ctypes.c_int, _vp, ctypes.c_int32)
+_sig("okpz_batch_get_cell_borders", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int32))
 _sig("okpz_get_cell_borders", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int32))
 _sig("okpz_sync", ctypes.c_int, _vp)
 _sig("okpz_free", ctypes.c_int, _vp)
@@ -125,7 +127,8 @@ EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads",
             "okpz_set_cell_borders", "okpz_get_cell_borders", "okpz_sync",
             "okpz_free", "okpz_last_error", "okpz_batch_create", "okpz_batch_set_mapping",
-            "okpz_batch_get_mapping", "okpz_batch_autotune", "okpz_batch_run",
+            "okpz_batch_get_mapping", "okpz_batch_set_cell_borders",
+            "okpz_batch_get_cell_borders", "okpz_batch_autotune", "okpz_batch_run",
             "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
             "okpz_batch_w2_histogram", "okpz_batch_w2_cumulants", "okpz_batch_psi",
             "okpz_serve_create", "okpz_serve_set_mapping",
@@ -309,6 +312,15 @@ class Batch:
 
     def set_mapping(self, threads: int, workgroups: int = 0) -> None:
         _bcheck(_lib.okpz_batch_set_mapping(self._h, int(threads), int(workgroups)))
+
+    def set_cell_borders(self, kind: int) -> None:
+        """OKPZ_CELLS_DEAD (default) or OKPZ_CELLS_DELAYED for every job."""
+        _bcheck(_lib.okpz_batch_set_cell_borders(self._h, int(kind)))
+
+    def cell_borders(self) -> int:
+        k = ctypes.c_int32()
+        _bcheck(_lib.okpz_batch_get_cell_borders(self._h, ctypes.byref(k)))
+        return k.value
 
     def mapping(self) -> tuple:
         t, w = ctypes.c_int32(), ctypes.c_int32()

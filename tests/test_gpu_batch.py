@@ -28,9 +28,10 @@ def okpz():
     return m
 
 
-def alone(okpz, job, m):
+def alone(okpz, job, m, cells=0):
     Lx, Ly, p, q, seed, t_max = job
     sim = okpz.okpz_init(Lx, Ly, p, q, seed)
+    sim.set_cell_borders(cells)
     out = []
     for t in okpz.sampling_times(t_max, m):
         out.append((t,) + sim.width(t))
@@ -67,6 +68,29 @@ def test_batch_small_jobs_match_oracle(okpz):
         assert np.array_equal(b.get_lattice(r), lat) and b.h0(r) == H0
         t, s1, s2 = b.samples(r)
         assert t[-1] == t_max and (s1[-1], s2[-1]) == oracle.width_sums(lat, H0)
+    b.free()
+
+
+@pytest.mark.parametrize("threads,wgs", [(256, 0), (512, 0), (1024, 5)])
+def test_delayed_cell_borders_in_a_batch(okpz, threads, wgs):
+    # every job of a delayed-border batch follows its lone delayed-border
+    # trajectory (itself pinned to the oracle); small jobs also checked
+    # against the oracle directly
+    D = okpz.OKPZ_CELLS_DELAYED
+    refs = [alone(okpz, j, M, D) for j in MIXED]
+    b = okpz.Batch(MIXED, M)
+    b.set_cell_borders(D)
+    assert b.cell_borders() == D
+    b.set_mapping(threads, wgs)
+    b.run()
+    check_batch(okpz, b, MIXED, M, refs)
+    for r in (0, 3):
+        Lx, Ly, p, q, seed, t_max = MIXED[r]
+        lat = oracle.flat(Lx, Ly)
+        H0 = oracle.run(lat, p, q, seed, 0, t_max, 0, delayed=True)
+        assert np.array_equal(b.get_lattice(r), lat) and b.h0(r) == H0
+    with pytest.raises(okpz.OkpzError):
+        b.set_cell_borders(7)
     b.free()
 
 

@@ -61,7 +61,8 @@ def test_flat_state_has_an_empty_axis_spectrum(okpz, Lx, Ly):
 
 
 @pytest.mark.parametrize("Lx,Ly,seed", [(32, 32, 1), (64, 128, 2), (128, 64, 3), (256, 256, 4),
-                                        (1024, 512, 5), (2048, 2048, 6), (8192, 32, 7)])
+                                        (1024, 512, 5), (2048, 2048, 6), (8192, 32, 7),
+                                        (131072, 32, 8), (32, 131072, 9)])
 def test_rough_surfaces_match_oracle(okpz, Lx, Ly, seed):
     lat, H0 = inputs.rough_state(Lx, Ly, seed=seed, mcs=4)
     sim = okpz.okpz_init(Lx, Ly, 0.9, 0.2, seed)
