@@ -204,6 +204,30 @@ def copy_calibration(nbytes=1 << 30):
     del a, b
 
 
+def size_scan(okpz, sizes, budget_ms=150.0):
+    """Device time per MCS of one lattice per size (flat start, p = 1, q = 0,
+    seed 1), from HIP events on the lattice's stream: the per-lattice path
+    across sizes, where small lattices cannot fill the device."""
+    import torch
+
+    out = []
+    for L in sizes:
+        sim = okpz.okpz_init(L, L, 1.0, 0.0, 1)
+        sim.sweep(2)
+        st = torch.cuda.ExternalStream(sim.stream())
+        n = max(4, min(4000, int(budget_ms * 1.3e9 / (L * L))))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        sim.sweep(n)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        out.append({"L": L, "mcs": n, "ms_per_mcs": ms, "site_updates_per_s": L * L / (ms * 1e-3),
+                    "ns_per_site": ms * 1e6 / (L * L)})
+        sim.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +242,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving leg: jobs (0 skips it)")
     ap.add_argument("--cell-borders", choices=("dead", "delayed"), default="dead",
                     help="thread-cell borders of the tiled dynamics")
+    ap.add_argument("--size-scan", type=int, default=1,
+                    help="1: time one lattice per size 2^8 .. 2^16 (0 skips it)")
     ap.add_argument("--psd-calls", type=int, default=3,
                     help="spectrum of the final surface: timed calls (0 skips it)")
     args = ap.parse_args()
@@ -309,6 +335,9 @@ def main():
     del buf
     torch.cuda.synchronize()
     log(f"sweep leg: {sweep_ms:.3f} ms per MCS, {value:.4g} site updates/s")
+    if args.size_scan:
+        out["size_scan"] = size_scan(okpz, [1 << k for k in range(8, 17)])
+        log("size scan done")
     if args.batch_scale > 0:
         out["batched_vs_plain"] = batch_leg(args.batch_scale)
         log(f"ensemble leg: speedup {out['batched_vs_plain']['speedup']:.3g}")
