@@ -85,10 +85,11 @@ int okpz_w2(okpz_sim *s, double *w2);
  * height is subtracted).  One surface: the ensemble average of Eq. (PSD) and
  * the average over the two directions are the caller's means over calls and
  * over sx, sy.  sx and sy are host arrays of Lx/2+1 and Ly/2+1 doubles; either
- * may be NULL.  The profiles are exact integers; the transform is fp64.
- * Both sides must be powers of two (OKPZ_EINVAL otherwise).  The first call
- * allocates at most min(32 MiB, Lx*Ly/4) + 40*max(Lx,Ly) bytes (plus
- * alignment) of device scratch, kept until okpz_free.  Synchronous. */
+ * may be NULL.  The profiles are exact integers; the transform is fp64
+ * (radix 2 for a power-of-two side, Bluestein's chirp-z form otherwise).
+ * The first call allocates at most min(32 MiB, Lx*Ly/4) + 40*max(Lx,Ly)
+ * bytes of device scratch (plus 128*max(Lx,Ly) when a side is not a power of
+ * two), kept until okpz_free.  Synchronous. */
 int okpz_psd(okpz_sim *s, double *sx, double *sy);
 
 /* Current time in MCS, and the absolute height H0 = h(0,0) (synchronous). */

@@ -90,13 +90,14 @@ size_t width_scratch_words(int64_t Ly);
 // The per-row pass alone (rows[0..3 Ly) as above, no combine).
 hipError_t launch_width_rows(const LatticeView &v, int64_t *rows, hipStream_t st);
 
-// Power spectrum along the lattice axes (power-of-two sides): scratch layout
+// Power spectrum along the lattice axes: scratch layout
 // (byte offsets into one device allocation of `bytes`) and launch.  Needs the
 // rows of launch_width_rows; leaves S along x (Lx/2+1 doubles) followed by S
 // along y (Ly/2+1 doubles) at off_spec.
 struct PsdPlan {
     int32_t R, nch;  // rows per column-count chunk, number of chunks
-    size_t off_cnt, off_zx, off_zy, off_spec, off_blk, bytes;
+    size_t off_cnt, off_zx, off_zy, off_spec, off_blk, off_conv, bytes;
+    int64_t conv_len;  // Bluestein transform length (0: both sides powers of two)
 };
 bool psd_shape_ok(int64_t Lx, int64_t Ly);
 PsdPlan psd_plan(int64_t Lx, int64_t Ly);

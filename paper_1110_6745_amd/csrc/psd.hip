@@ -14,6 +14,11 @@
 // radix-2 decimation-in-frequency FFT in fp64: global passes while a
 // butterfly's span exceeds the LDS tile, then one LDS-resident pass per tile;
 // the output stays in bit-reversed order and the spectrum kernel reads it so.
+// A side that is not a power of two goes through Bluestein's chirp-z form
+// (Bluestein 1970): with c_j = exp(-i pi j^2 / n), X_k = c_k sum_j (x_j c_j)
+// conj(c_{k-j}), a convolution done with power-of-two transforms of length
+// M >= 2n - 1 (forward stages, a pointwise product in bit-reversed order, and
+// the forward stages undone in reverse order, which returns natural order).
 #include "width_core.h"
 
 namespace okpz {
@@ -213,6 +218,21 @@ __device__ __forceinline__ void dif_butterfly(double2 &a, double2 &b, int r, int
     b = make_double2(dx * c - dy * s, dx * s + dy * c);
 }
 
+// The stage above undone without its factor 1/2: (a, b) <- (a + t, a - t),
+// t = b e^{+i pi r / h}.  All stages undone in reverse order turn the
+// bit-reversed transform of x back into n x in natural order, i.e. they
+// apply the unnormalised inverse DFT to a bit-reversed spectrum.
+__device__ __forceinline__ void dif_butterfly_undo(double2 &a, double2 &b, int r, int h)
+{
+    double s, c;
+    sincospi((double)r / h, &s, &c);
+    const double2 t = make_double2(b.x * c - b.y * s, b.x * s + b.y * c);
+    const double2 u = a;
+    a = make_double2(u.x + t.x, u.y + t.y);
+    b = make_double2(u.x - t.x, u.y - t.y);
+}
+
+template <bool kUndo>
 __global__ __launch_bounds__(kFftThreads) void fft_stage_kernel(double2 *z, int32_t n, int32_t h)
 {
     const int i = blockIdx.x * kFftThreads + threadIdx.x;  // butterfly index
@@ -220,25 +240,33 @@ __global__ __launch_bounds__(kFftThreads) void fft_stage_kernel(double2 *z, int3
     const int r = i & (h - 1);
     const int lo = ((i - r) << 1) + r;
     double2 a = z[lo], b = z[lo + h];
-    dif_butterfly(a, b, r, h);
+    if (kUndo)
+        dif_butterfly_undo(a, b, r, h);
+    else
+        dif_butterfly(a, b, r, h);
     z[lo] = a;
     z[lo + h] = b;
 }
 
-// The remaining stages (spans T/2 .. 1) of one contiguous tile of T values
-// in LDS.
+// The stages of spans T/2 .. 1 (undone: 1 .. T/2) of one contiguous tile of
+// T values, in LDS.
+template <bool kUndo>
 __global__ __launch_bounds__(kFftThreads) void fft_tile_kernel(double2 *z, int32_t T)
 {
     __shared__ double2 tile[kTile];
     double2 *g = z + (size_t)blockIdx.x * T;
     for (int i = threadIdx.x; i < T; i += kFftThreads) tile[i] = g[i];
     __syncthreads();
-    for (int h = T >> 1; h >= 1; h >>= 1) {
+    for (int k = 0; (1 << k) < T; ++k) {
+        const int h = kUndo ? (1 << k) : (T >> (k + 1));
         for (int i = threadIdx.x; i < (T >> 1); i += kFftThreads) {
             const int r = i & (h - 1);
             const int lo = ((i - r) << 1) + r;
             double2 a = tile[lo], b = tile[lo + h];
-            dif_butterfly(a, b, r, h);
+            if (kUndo)
+                dif_butterfly_undo(a, b, r, h);
+            else
+                dif_butterfly(a, b, r, h);
             tile[lo] = a;
             tile[lo + h] = b;
         }
@@ -247,14 +275,63 @@ __global__ __launch_bounds__(kFftThreads) void fft_tile_kernel(double2 *z, int32
     for (int i = threadIdx.x; i < T; i += kFftThreads) g[i] = tile[i];
 }
 
-// S(n) = |Z(n)|^2 / (Lx Ly) for n = 0 .. len/2 from the bit-reversed
-// transform; S(0) = 0 exactly (the mean is subtracted by definition).
+// c_j = exp(-i pi j^2 / n), the phase reduced exactly: j^2 mod 2n.
+__device__ __forceinline__ double2 chirp(int64_t j, int32_t n)
+{
+    const int64_t k = (j * j) % (2 * (int64_t)n);
+    double s, c;
+    sincospi(-(double)k / n, &s, &c);
+    return make_double2(c, s);
+}
+
+// A = (x_j c_j, then zeros) and B = (conj(c_m) at m and M - m for m < n,
+// zeros between), both of length M.
+__global__ void chirp_kernel(const double2 *x, int32_t n, int32_t M, double2 *A, double2 *B)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    if (j < n) {
+        const double2 c = chirp(j, n), v = x[j];
+        A[j] = make_double2(v.x * c.x - v.y * c.y, v.x * c.y + v.y * c.x);
+    } else {
+        A[j] = make_double2(0.0, 0.0);
+    }
+    const int m = j < n ? j : (j > M - n ? M - j : -1);
+    if (m >= 0) {
+        const double2 c = chirp(m, n);
+        B[j] = make_double2(c.x, -c.y);
+    } else {
+        B[j] = make_double2(0.0, 0.0);
+    }
+}
+
+__global__ void cmul_kernel(double2 *A, const double2 *B, int32_t M)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    const double2 a = A[j], b = B[j];
+    A[j] = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// X_k = c_k conv_k, conv = (the undone transform) / M, natural order.
+__global__ void unchirp_kernel(const double2 *conv, int32_t n, int32_t M, double2 *x)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double2 c = chirp(k, n), v = conv[k];
+    const double inv = 1.0 / M;
+    x[k] = make_double2((v.x * c.x - v.y * c.y) * inv, (v.x * c.y + v.y * c.x) * inv);
+}
+
+// S(n) = |Z(n)|^2 / (Lx Ly) for n = 0 .. len/2 from the transform, in
+// bit-reversed order (log2len > 0) or natural order (log2len = 0); S(0) = 0
+// exactly (the mean is subtracted by definition).
 __global__ void spectrum_kernel(const double2 *z, int32_t len, int32_t log2len, double norm,
                                 double *S)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k > (len >> 1)) return;
-    const uint32_t j = __brev((uint32_t)k) >> (32 - log2len);
+    const uint32_t j = log2len > 0 ? __brev((uint32_t)k) >> (32 - log2len) : (uint32_t)k;
     const double2 v = z[j];
     S[k] = k == 0 ? 0.0 : (v.x * v.x + v.y * v.y) * norm;
 }
@@ -266,23 +343,64 @@ int log2_exact(int32_t n)
     return l;
 }
 
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Bluestein length for a side n: the power of two M >= 2n - 1.
+int64_t conv_len(int64_t n)
+{
+    int64_t M = 1;
+    while (M < 2 * n - 1) M <<= 1;
+    return M;
+}
+
+// Forward transform of n = 2^k values in place, output bit-reversed.
 hipError_t launch_fft(double2 *z, int32_t n, hipStream_t st)
 {
     const int T = n < kTile ? n : kTile;
     for (int32_t h = n >> 1; 2 * h > T; h >>= 1)
-        hipLaunchKernelGGL(fft_stage_kernel, dim3((n / 2 + kFftThreads - 1) / kFftThreads),
+        hipLaunchKernelGGL(fft_stage_kernel<false>, dim3((n / 2 + kFftThreads - 1) / kFftThreads),
                            dim3(kFftThreads), 0, st, z, n, h);
-    hipLaunchKernelGGL(fft_tile_kernel, dim3(n / T), dim3(kFftThreads), 0, st, z, T);
+    hipLaunchKernelGGL(fft_tile_kernel<false>, dim3(n / T), dim3(kFftThreads), 0, st, z, T);
+    return hipGetLastError();
+}
+
+// launch_fft undone: bit-reversed spectrum in, n x the inverse DFT out.
+hipError_t launch_fft_undo(double2 *z, int32_t n, hipStream_t st)
+{
+    const int T = n < kTile ? n : kTile;
+    hipLaunchKernelGGL(fft_tile_kernel<true>, dim3(n / T), dim3(kFftThreads), 0, st, z, T);
+    for (int32_t h = T; h < n; h <<= 1)
+        hipLaunchKernelGGL(fft_stage_kernel<true>, dim3((n / 2 + kFftThreads - 1) / kFftThreads),
+                           dim3(kFftThreads), 0, st, z, n, h);
+    return hipGetLastError();
+}
+
+// The DFT of the n values of z, in place: bit-reversed when n is a power of
+// two (returns log2 n), natural order through Bluestein otherwise (returns 0);
+// A and B hold conv_len(n) values each.
+hipError_t transform(double2 *z, int32_t n, double2 *A, double2 *B, int *order, hipStream_t st)
+{
+    if (pow2(n)) {
+        *order = log2_exact(n);
+        return launch_fft(z, n, st);
+    }
+    *order = 0;
+    const int32_t M = (int32_t)conv_len(n);
+    hipLaunchKernelGGL(chirp_kernel, dim3((M + 255) / 256), dim3(256), 0, st, z, n, M, A, B);
+    hipError_t e = launch_fft(A, M, st);
+    if (e != hipSuccess) return e;
+    e = launch_fft(B, M, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cmul_kernel, dim3((M + 255) / 256), dim3(256), 0, st, A, B, M);
+    e = launch_fft_undo(A, M, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(unchirp_kernel, dim3((n + 255) / 256), dim3(256), 0, st, A, n, M, z);
     return hipGetLastError();
 }
 
 }  // namespace
 
-bool psd_shape_ok(int64_t Lx, int64_t Ly)
-{
-    auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
-    return pow2(Lx) && pow2(Ly);
-}
+bool psd_shape_ok(int64_t Lx, int64_t Ly) { return Lx >= 32 && Ly >= 32; }
 
 PsdPlan psd_plan(int64_t Lx, int64_t Ly)
 {
@@ -300,7 +418,12 @@ PsdPlan psd_plan(int64_t Lx, int64_t Ly)
     p.off_spec = p.off_zy + al((size_t)Ly * 16);
     p.off_blk = p.off_spec + al((size_t)(Lx / 2 + 1 + Ly / 2 + 1) * 8);
     const size_t nbx = (Lx + kProfThreads - 1) / kProfThreads, nby = (Ly + kProfThreads - 1) / kProfThreads;
-    p.bytes = p.off_blk + al((2 * (nbx + nby) + 4) * 8);
+    p.off_conv = p.off_blk + al((2 * (nbx + nby) + 4) * 8);
+    int64_t M = 0;  // Bluestein buffers, shared by the two sides in turn
+    if (!pow2(Lx)) M = conv_len(Lx);
+    if (!pow2(Ly) && conv_len(Ly) > M) M = conv_len(Ly);
+    p.conv_len = M;
+    p.bytes = p.off_conv + 2 * al((size_t)M * 16);
     return p;
 }
 
@@ -333,15 +456,18 @@ hipError_t launch_psd(const LatticeView &v, const PsdPlan &p, const int64_t *row
                        v.Lx, v.Ly, v.ox, bx, nbx, zx);
     hipLaunchKernelGGL(profile_write_kernel<true>, dim3(nby), dim3(kProfThreads), 0, st, cnt, rows,
                        v.Lx, v.Ly, v.ox, by, nby, zy);
-    hipError_t e = launch_fft(zx, v.Lx, st);
+    double2 *A = reinterpret_cast<double2 *>(base + p.off_conv);
+    double2 *B = reinterpret_cast<double2 *>(base + p.off_conv + (p.bytes - p.off_conv) / 2);
+    int ox_order = 0, oy_order = 0;
+    hipError_t e = transform(zx, v.Lx, A, B, &ox_order, st);
     if (e != hipSuccess) return e;
-    e = launch_fft(zy, v.Ly, st);
+    e = transform(zy, v.Ly, A, B, &oy_order, st);
     if (e != hipSuccess) return e;
     const double norm = 1.0 / ((double)v.Lx * (double)v.Ly);
     hipLaunchKernelGGL(spectrum_kernel, dim3((v.Lx / 2 + 256) / 256), dim3(256), 0, st, zx, v.Lx,
-                       log2_exact(v.Lx), norm, spec);
+                       ox_order, norm, spec);
     hipLaunchKernelGGL(spectrum_kernel, dim3((v.Ly / 2 + 256) / 256), dim3(256), 0, st, zy, v.Ly,
-                       log2_exact(v.Ly), norm, spec + v.Lx / 2 + 1);
+                       oy_order, norm, spec + v.Lx / 2 + 1);
     return hipGetLastError();
 }
 

@@ -216,7 +216,7 @@ class Sim:
     def psd(self) -> tuple:
         """(Sx, Sy): the surface's power spectrum along the x axis for
         k = 2 pi n / Lx, n = 0 .. Lx/2, and along the y axis for n = 0 .. Ly/2
-        (Eqs. (PSD), (hF); power-of-two sides)."""
+        (Eqs. (PSD), (hF))."""
         Lx, Ly = self.Lx, self.Ly
         sx = np.empty(Lx // 2 + 1, dtype=np.float64)
         sy = np.empty(Ly // 2 + 1, dtype=np.float64)
