@@ -339,6 +339,8 @@ int okpz_init(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64
 int okpz_init_on(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
                  void *dev_buf, size_t bytes, void *hip_stream)
 {
+    if (!out) return fail(OKPZ_EINVAL, "out is NULL");
+    *out = nullptr;
     okpz_sim *s = nullptr;
     int rc = make_sim(&s, Lx, Ly, p, q, seed, dev_buf, bytes, hip_stream);
     if (rc != OKPZ_OK) return rc;

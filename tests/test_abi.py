@@ -72,3 +72,20 @@ def test_sampling_times_follow_the_paper_recurrence():
     assert okpz.sampling_times(100, 0.01)[:4] == [11, 21, 31, 42]
     assert okpz.sampling_times(100, 0.01)[-1] == 100
     assert okpz.sampling_times(0, 0.01) == []
+
+
+def test_header_is_c99_and_host_calls_work_from_c(tmp_path):
+    # a plain C client compiled as strict C99 against include/okpz.h and
+    # linked with the library; its host-only calls run without a GPU
+    import subprocess
+
+    exe = str(tmp_path / "client")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c", "okpz_c_client.c"),
+                    "-L", os.path.join(ROOT, "paper_1110_6745_amd"), "-lokpz",
+                    "-Wl,-rpath," + os.path.join(ROOT, "paper_1110_6745_amd"), "-o", exe],
+                   check=True)
+    out = subprocess.run([exe, "host"], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "host ok"
