@@ -11,6 +11,8 @@
 
 #include "okpz.h"
 #include "okpz_internal.h"
+#include "psd.h"
+#include "width.h"
 
 struct okpz_sim {
     int64_t Lx, Ly;

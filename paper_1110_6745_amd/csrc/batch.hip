@@ -36,6 +36,7 @@
 
 #include "okpz.h"
 #include "sweep_core.h"
+#include "width.h"
 #include "width_core.h"
 
 namespace okpz {

@@ -80,28 +80,4 @@ hipError_t launch_init(uint32_t *planes, int32_t Ly, int32_t W, hipStream_t st);
 hipError_t launch_sweep(const SweepLaunch &a, int threads, hipStream_t st);
 bool sweep_threads_ok(int threads);
 
-// Width: per-row partial sums into `rows` scratch (width_scratch_words(Ly)
-// int64: 3 Ly row values, then per-block records), then a two-level combine
-// into out[0..3] = {S1' lo, S1' hi, S2' lo, S2' hi} (128-bit two's
-// complement halves of the sums relative to H0).
-hipError_t launch_width(const LatticeView &v, int64_t *rows, int64_t *out, hipStream_t st);
-
-size_t width_scratch_words(int64_t Ly);
-// The per-row pass alone (rows[0..3 Ly) as above, no combine).
-hipError_t launch_width_rows(const LatticeView &v, int64_t *rows, hipStream_t st);
-
-// Power spectrum along the lattice axes: scratch layout
-// (byte offsets into one device allocation of `bytes`) and launch.  Needs the
-// rows of launch_width_rows; leaves S along x (Lx/2+1 doubles) followed by S
-// along y (Ly/2+1 doubles) at off_spec.
-struct PsdPlan {
-    int32_t R, nch;  // rows per column-count chunk, number of chunks
-    size_t off_cnt, off_zx, off_zy, off_spec, off_blk, off_conv, bytes;
-    int64_t conv_len;  // Bluestein transform length (0: both sides powers of two)
-};
-bool psd_shape_ok(int64_t Lx, int64_t Ly);
-PsdPlan psd_plan(int64_t Lx, int64_t Ly);
-hipError_t launch_psd(const LatticeView &v, const PsdPlan &p, const int64_t *rows, void *scratch,
-                      hipStream_t st);
-
 }  // namespace okpz

@@ -19,6 +19,7 @@
 // conj(c_{k-j}), a convolution done with power-of-two transforms of length
 // M >= 2n - 1 (forward stages, a pointwise product in bit-reversed order, and
 // the forward stages undone in reverse order, which returns natural order).
+#include "psd.h"
 #include "width_core.h"
 
 namespace okpz {

@@ -11,6 +11,7 @@
 // the delta_b into G_b and adds the blocks up.  Up to kOneGroupRows rows one
 // workgroup combines the rows directly (one launch less, which is what a
 // small lattice's measurement costs).
+#include "width.h"
 #include "width_core.h"
 
 namespace okpz {
