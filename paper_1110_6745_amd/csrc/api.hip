@@ -453,9 +453,6 @@ int okpz_w2(okpz_sim *s, double *w2)
 int okpz_psd(okpz_sim *s, double *sx, double *sy)
 {
     if (!s) return fail(OKPZ_EINVAL, "null handle");
-    if (!okpz::psd_shape_ok(s->Lx, s->Ly))
-        return fail(OKPZ_EINVAL, "the spectrum needs power-of-two sides (lattice %lldx%lld)",
-                    (long long)s->Lx, (long long)s->Ly);
     const okpz::PsdPlan p = okpz::psd_plan(s->Lx, s->Ly);
     if (!s->psd_mem) {
         hipError_t e = hipMalloc(&s->psd_mem, p.bytes);

@@ -14,7 +14,6 @@ struct PsdPlan {
     size_t off_cnt, off_zx, off_zy, off_spec, off_blk, off_conv, bytes;
     int64_t conv_len;  // Bluestein transform length (0: both sides powers of two)
 };
-bool psd_shape_ok(int64_t Lx, int64_t Ly);
 PsdPlan psd_plan(int64_t Lx, int64_t Ly);
 hipError_t launch_psd(const LatticeView &v, const PsdPlan &p, const int64_t *rows, void *scratch,
                       hipStream_t st);

@@ -401,8 +401,6 @@ hipError_t transform(double2 *z, int32_t n, double2 *A, double2 *B, int *order, 
 
 }  // namespace
 
-bool psd_shape_ok(int64_t Lx, int64_t Ly) { return Lx >= 32 && Ly >= 32; }
-
 PsdPlan psd_plan(int64_t Lx, int64_t Ly)
 {
     PsdPlan p{};
