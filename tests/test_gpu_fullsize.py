@@ -9,6 +9,8 @@
   a few MCS.
 * Rows of full length 2^17 and columns of full height 2^17 for the width
   path, on oracle-made rough states.
+* A 2^19 x 2^19 lattice, whose sweep is split over two launches, on
+  sampled blocks; the longest sides taken (2^20 x 32, 32 x 2^20) whole.
 """
 import numpy as np
 import pytest
@@ -128,4 +130,22 @@ def test_sweep_split_over_launches_at_2_19(okpz):
             assert np.array_equal(got_rows[:, xs], blk), f"block ({i},{j}) differs"
         print(f"block row {j} ok", flush=True)
     assert sim.h0() == dh_total
+    sim.free()
+
+
+@pytest.mark.parametrize("Lx,Ly", [(1 << 20, 32), (32, 1 << 20)])
+def test_longest_sides(okpz, Lx, Ly):
+    # the largest side the library takes (2^20) against the smallest (32):
+    # sweeps, exact width and the spectrum (a 2^20-point transform)
+    from oracle import psd as P
+    from tests.test_gpu_psd import check
+
+    lat, H0 = inputs.rough_state(Lx, Ly, seed=41, mcs=1)
+    sim = okpz.okpz_init(Lx, Ly, 0.9, 0.15, 41)
+    sim.set_lattice(lat, H0, 7)
+    sim.sweep(3)
+    H1 = oracle.run(lat, 0.9, 0.15, 41, 7, 3, H0)
+    assert sim.width() == oracle.width_sums(lat, H1)
+    assert np.array_equal(sim.get_lattice(), lat) and sim.h0() == H1
+    check(sim.psd(), lat, H1, f"{Lx}x{Ly}")
     sim.free()
