@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy
 # (profiles/sweep_kernel_L131072_hbm_counters.md).  Reported only while the
 # sweep sources hash to the value the counters were taken on.
-TRAFFIC_MEASURED = {"sources_sha256_16": "043a1e4cdf909484", "L": 1 << 17, "bytes": 8.625e9}
+TRAFFIC_MEASURED = {"sources_sha256_16": "db20f0f8c8988de7", "L": 1 << 17, "bytes": 8.625e9}
 SWEEP_SOURCES = ("sweep_core.h", "sweep.hip", "okpz_internal.h")
 METRIC = "site updates/s (+% HBM roofline) at L=2^17; realizations/s batched vs plain; serving p50/p99"
 

@@ -123,9 +123,9 @@ __device__ __forceinline__ void run_group(const SweepLaunch &a, int b0, int G, u
     const int tiles = ((G * (a.By + 1) * a.Bx) + 15) & ~15;
     uint32_t *opk = reinterpret_cast<uint32_t *>(smem + tiles);
     if (a.Bx == core::kMaxB && a.By == core::kMaxB)
-        core::sweep_group<kThreads, kMode, core::kMaxB>(a, b0, 1, smem, opk);
+        core::sweep_group<kThreads, kMode, core::kMaxB, true>(a, b0, 1, smem, opk);
     else
-        core::sweep_group<kThreads, kMode, 0>(a, b0, G, smem, opk);
+        core::sweep_group<kThreads, kMode, 0, true>(a, b0, G, smem, opk);
 }
 
 // Publish job r's next sweep (or count it finished).  Thread 0 only, after
@@ -259,9 +259,11 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
         if (tid == 0) {
             s_width = 0;
             // release this item's lattice words; the last item acquires all
-            const uint32_t d = __hip_atomic_fetch_add(&state[r].done, 1u, __ATOMIC_ACQ_REL,
+            // (the increments form one release sequence)
+            const uint32_t d = __hip_atomic_fetch_add(&state[r].done, 1u, __ATOMIC_RELEASE,
                                                       __HIP_MEMORY_SCOPE_AGENT) + 1u;
             if (d == (uint32_t)jd.nitems) {  // last item of sweep s: advance the job
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 JobState ns = js;
                 ns.s = js.s + 1;
                 ns.ox = a.sx;

@@ -127,12 +127,6 @@ __host__ __device__ inline int group_size(int Bx, int By, int nblk)
     return g < 1 ? 1 : g;
 }
 
-// One sweep of blocks [b0, b0 + G) of the lattice described by `a`.
-//   kFixedB = 256: 256 x 256 blocks, G = 1, static geometry (the three LDS
-//                  addresses of an attempt are one register plus offsets);
-//   kFixedB = 0:   any block sides 32..256, geometry from `a`.
-// smem: at least G * (By + 1) * Bx bytes; opk: G * 35 words of LDS (origins,
-// then the blocks' placement when kFixedB = 0).
 // Eq. (1) on the five-bit code of a site byte s, its left neighbour's byte l
 // and its lower neighbour's byte d; r is the attempt's acceptance draw
 // (kDraw only).
@@ -166,7 +160,16 @@ __device__ __forceinline__ void xor_byte(uint8_t *smem, uint32_t off, uint32_t v
     atomicXor(w, v << (8 * (off & 3u)));
 }
 
-template <int kThreads, int kModeFull, int kFixedB>
+// One sweep of blocks [b0, b0 + G) of the lattice described by `a`.
+//   kFixedB = 256: 256 x 256 blocks, G = 1, static geometry (the three LDS
+//                  addresses of an attempt are one register plus offsets);
+//   kFixedB = 0:   any block sides 32..256, geometry from `a`.
+// smem: at least G * (By + 1) * Bx bytes; opk: G * 35 words of LDS (origins,
+// then the blocks' placement when kFixedB = 0).
+// kStoreThrough: write the new lattice with system-scope stores, which go
+// through to memory instead of staying dirty in this XCD's L2 (the persistent
+// kernel's hand-over to other XCDs then has little to write back).
+template <int kThreads, int kModeFull, int kFixedB, bool kStoreThrough = false>
 __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const int G,
                                             uint8_t *__restrict__ smem, uint32_t *opk)
 {
@@ -490,8 +493,14 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             byw |= yb << (8 * b);
         }
         const size_t col = (size_t)bi * wpr + k;
-        a.dst[(size_t)y * a.W + col] = ~bxw;  // back to sigma = +1 bits
-        a.dst[((size_t)a.Ly + y) * a.W + col] = ~byw;
+        uint32_t *w0 = a.dst + (size_t)y * a.W + col, *w1 = a.dst + ((size_t)a.Ly + y) * a.W + col;
+        if (kStoreThrough) {
+            __hip_atomic_store(w0, ~bxw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(w1, ~byw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        } else {
+            *w0 = ~bxw;  // back to sigma = +1 bits
+            *w1 = ~byw;
+        }
     }
 }
 
