@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy
 # (profiles/sweep_kernel_L131072_hbm_counters.md).  Reported only while the
 # sweep sources hash to the value the counters were taken on.
-TRAFFIC_MEASURED = {"sources_sha256_16": "db20f0f8c8988de7", "L": 1 << 17, "bytes": 8.625e9}
+TRAFFIC_MEASURED = {"sources_sha256_16": "6a92783189a6ae65", "L": 1 << 17, "bytes": 8.625e9}
 SWEEP_SOURCES = ("sweep_core.h", "sweep.hip", "okpz_internal.h")
 METRIC = "site updates/s (+% HBM roofline) at L=2^17; realizations/s batched vs plain; serving p50/p99"
 
@@ -244,6 +244,8 @@ def main():
                     help="thread-cell borders of the tiled dynamics")
     ap.add_argument("--size-scan", type=int, default=1,
                     help="1: time one lattice per size 2^8 .. 2^16 (0 skips it)")
+    ap.add_argument("--in-place", action="store_true",
+                    help="one lattice copy updated in place (fits 2^20 x 2^20 on one GPU)")
     ap.add_argument("--psd-calls", type=int, default=3,
                     help="spectrum of the final surface: timed calls (0 skips it)")
     args = ap.parse_args()
@@ -263,10 +265,15 @@ def main():
     L = args.L
     p, q, seed = 1.0, 0.0, 1
     N = L * L
-    nbytes = okpz.okpz_required_bytes(L, L)
-    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    sim = okpz.okpz_init_on(L, L, p, q, seed, buf.data_ptr(), nbytes, stream.cuda_stream)
+    if args.in_place:
+        nbytes = okpz.okpz_required_bytes_in_place(L, L)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        sim = okpz.okpz_init_in_place(L, L, p, q, seed, buf.data_ptr(), nbytes, stream.cuda_stream)
+    else:
+        nbytes = okpz.okpz_required_bytes(L, L)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        sim = okpz.okpz_init_on(L, L, p, q, seed, buf.data_ptr(), nbytes, stream.cuda_stream)
     sim.set_threads(args.threads)
     if args.cell_borders == "delayed":
         sim.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
@@ -295,7 +302,8 @@ def main():
     achieved_gbs = 0.5 * N / (sweep_ms * 1e-3) / 1e9
     w2 = [(t, (N * s2 - s1 * s1) / (N * N)) for t, s1, s2 in widths]
     traffic = None
-    if L == TRAFFIC_MEASURED["L"] and sweep_sources_hash() == TRAFFIC_MEASURED["sources_sha256_16"]:
+    if (L == TRAFFIC_MEASURED["L"] and not args.in_place
+            and sweep_sources_hash() == TRAFFIC_MEASURED["sources_sha256_16"]):
         traffic = TRAFFIC_MEASURED["bytes"]
 
     out = {
@@ -315,7 +323,8 @@ def main():
                                f"MCS {t_lo}..{t_hi}, exact W^2 at t_(i+1)=(t_i+10)e^0.01",
                    "Lx": L, "Ly": L, "p": p, "q": q, "seed": seed,
                    "width_samples": len(widths), "threads_per_workgroup": args.threads,
-                   "cell_borders": args.cell_borders},
+                   "cell_borders": args.cell_borders,
+                   "lattice_copies": 1 if args.in_place else 2},
         "sweep_kernel_ms": sweep_ms,
         "sweep_site_updates_per_s": N / (sweep_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,

@@ -63,6 +63,29 @@ int okpz_init(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64
 int okpz_init_on(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
                  void *dev_buf, size_t bytes, void *hip_stream);
 
+/* Device bytes of a simulation that keeps ONE lattice copy and updates it in
+ * place: half the lattice bytes of okpz_required_bytes, which is what lets a
+ * 2^20 x 2^20 lattice (2^40 sites, 256 GiB) fit on one 288 GB GPU.  0 for an
+ * invalid size. */
+size_t okpz_required_bytes_in_place(int64_t Lx, int64_t Ly);
+
+/* As okpz_init_on (dev_buf NULL: the library allocates memory and a stream;
+ * otherwise at least okpz_required_bytes_in_place bytes, 256-byte aligned),
+ * but with one lattice copy that every sweep updates in place.  The
+ * trajectory is the one of a two-copy simulation with the same seed, bit for
+ * bit: the blocks of a sweep (Sec. II) cover disjoint sites and each reads
+ * and writes only its own, so the order in which blocks run cannot show.
+ * Horizontally adjacent blocks share a memory word at their common edge, so
+ * a sweep runs as two launches (even and odd block columns; three if the
+ * number of block columns is odd).  Every other call works on such a handle
+ * as on any other; its checkpoints restore as one-copy simulations. */
+int okpz_init_in_place(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
+                       void *dev_buf, size_t bytes, void *hip_stream);
+
+/* *copies = 2 for a simulation made by okpz_init, okpz_init_on or from a
+ * two-copy checkpoint, 1 for one updated in place. */
+int okpz_get_copies(const okpz_sim *s, int32_t *copies);
+
 /* Advance by n_mcs >= 0 Monte Carlo steps (Sec. II: one MCS = one overall
  * update, block-decomposition origin moved at every MCS).  Asynchronous on the
  * handle's stream.  Sweep indices must stay below 2^32. */

@@ -23,6 +23,7 @@ struct okpz_sim {
     uint32_t k0, k1;
     uint64_t Tp, Tq;
     uint32_t *buf[2];
+    int copies;  // 2: ping-pong copies; 1: one copy updated in place
     int cur;
     int32_t ox;
     int64_t t;
@@ -87,10 +88,16 @@ __global__ void init_flat_kernel(uint32_t *planes, int32_t Ly, int32_t W, int64_
 
 __global__ void set_h0_kernel(int64_t *h0, int64_t v) { *h0 = v; }
 
+size_t state_bytes(int64_t Lx, int64_t Ly, int copies)
+{
+    return copies * align_up(plane_bytes(Lx, Ly)) + 2 * kAlign +
+           align_up(okpz::width_scratch_words(Ly) * sizeof(int64_t));
+}
+
 int alloc_state(okpz_sim *s, void *dev_buf, size_t bytes, void *stream)
 {
     const size_t pb = align_up(plane_bytes(s->Lx, s->Ly));
-    const size_t need = okpz_required_bytes(s->Lx, s->Ly);
+    const size_t need = state_bytes(s->Lx, s->Ly, s->copies);
     if (dev_buf) {
         if (bytes < need)
             return fail(OKPZ_ENOMEM, "buffer of %zu bytes, %zu needed", bytes, need);
@@ -115,11 +122,12 @@ int alloc_state(okpz_sim *s, void *dev_buf, size_t bytes, void *stream)
         s->own_stream = true;
     }
     char *base = static_cast<char *>(s->mem);
+    const size_t cb = s->copies * pb;
     s->buf[0] = reinterpret_cast<uint32_t *>(base);
-    s->buf[1] = reinterpret_cast<uint32_t *>(base + pb);
-    s->d_h0 = reinterpret_cast<int64_t *>(base + 2 * pb);
-    s->d_out = reinterpret_cast<int64_t *>(base + 2 * pb + kAlign);
-    s->d_rows = reinterpret_cast<int64_t *>(base + 2 * pb + 2 * kAlign);
+    s->buf[1] = s->copies == 2 ? reinterpret_cast<uint32_t *>(base + pb) : s->buf[0];
+    s->d_h0 = reinterpret_cast<int64_t *>(base + cb);
+    s->d_out = reinterpret_cast<int64_t *>(base + cb + kAlign);
+    s->d_rows = reinterpret_cast<int64_t *>(base + cb + 2 * kAlign);
     return OKPZ_OK;
 }
 
@@ -134,7 +142,7 @@ void release(okpz_sim *s)
 }
 
 int make_sim(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
-             void *dev_buf, size_t bytes, void *stream)
+             void *dev_buf, size_t bytes, void *stream, int copies = 2)
 {
     if (!out) return fail(OKPZ_EINVAL, "out is NULL");
     *out = nullptr;
@@ -155,6 +163,7 @@ int make_sim(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_
     s->k1 = (uint32_t)(seed >> 32);
     s->Tp = okpz::threshold_of(p);
     s->Tq = okpz::threshold_of(q);
+    s->copies = copies;
     s->cur = 0;
     s->ox = 0;
     s->t = 0;
@@ -282,7 +291,8 @@ struct CkptHeader {
     double p, q;
     uint64_t seed;
     int64_t t, H0;
-    int32_t ox, pad2;
+    int32_t ox;
+    int32_t copies;  // 1 for a sim updated in place; 0 or 2 otherwise
 };
 
 }  // namespace
@@ -329,8 +339,13 @@ int okpz_geometry(int64_t Lx, int64_t Ly, int32_t *Bx, int32_t *By, int32_t *C)
 size_t okpz_required_bytes(int64_t Lx, int64_t Ly)
 {
     if (!size_ok(Lx) || !size_ok(Ly)) return 0;
-    return 2 * align_up(plane_bytes(Lx, Ly)) + 2 * kAlign +
-           align_up(okpz::width_scratch_words(Ly) * sizeof(int64_t));
+    return state_bytes(Lx, Ly, 2);
+}
+
+size_t okpz_required_bytes_in_place(int64_t Lx, int64_t Ly)
+{
+    if (!size_ok(Lx) || !size_ok(Ly)) return 0;
+    return state_bytes(Lx, Ly, 1);
 }
 
 int okpz_init(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed)
@@ -352,6 +367,30 @@ int okpz_init_on(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uin
         return rc;
     }
     *out = s;
+    return OKPZ_OK;
+}
+
+int okpz_init_in_place(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
+                       void *dev_buf, size_t bytes, void *hip_stream)
+{
+    if (!out) return fail(OKPZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    okpz_sim *s = nullptr;
+    int rc = make_sim(&s, Lx, Ly, p, q, seed, dev_buf, bytes, hip_stream, 1);
+    if (rc != OKPZ_OK) return rc;
+    rc = launch_flat(s);
+    if (rc != OKPZ_OK) {
+        release(s);
+        return rc;
+    }
+    *out = s;
+    return OKPZ_OK;
+}
+
+int okpz_get_copies(const okpz_sim *s, int32_t *copies)
+{
+    if (!s || !copies) return fail(OKPZ_EINVAL, "null argument");
+    *copies = s->copies;
     return OKPZ_OK;
 }
 
@@ -387,14 +426,17 @@ int okpz_sweep(okpz_sim *s, int64_t n_mcs)
         a.u00 = (int32_t)(x00 % s->g.Bx);
         a.v00 = (int32_t)(y00 % s->g.By);
         a.src = s->buf[s->cur];
-        a.dst = s->buf[s->cur ^ 1];
+        a.dst = s->buf[s->cur ^ (s->copies - 1)];
         a.ox_src = s->ox;
+        a.in_place = s->copies == 1 ? 1 : 0;
         a.sx = sx;
         a.sy = sy;
         a.s = sw;
         HIP_TRY(okpz::launch_sweep(a, s->threads, s->stream));
-        s->cur ^= 1;
-        s->ox = sx;
+        if (s->copies == 2) {  // the destination copy holds block column 0 at stored 0
+            s->cur ^= 1;
+            s->ox = sx;
+        }
         s->t += 1;
     }
     return OKPZ_OK;
@@ -551,6 +593,7 @@ int okpz_save(okpz_sim *s, void *buf, size_t *bytes)
     h.t = s->t;
     h.H0 = H0;
     h.ox = s->ox;
+    h.copies = s->copies;
     std::memcpy(buf, &h, sizeof h);
     HIP_TRY(hipMemcpy(static_cast<char *>(buf) + sizeof h, s->buf[s->cur], pb, hipMemcpyDeviceToHost));
     *bytes = need;
@@ -567,12 +610,12 @@ int okpz_load(okpz_sim **out, const void *buf, size_t bytes)
     if (std::memcmp(h.magic, "OKPZCKP1", 8) != 0 || h.version != 1)
         return fail(OKPZ_EINVAL, "not an okpz checkpoint");
     if (!size_ok(h.Lx) || !size_ok(h.Ly) || h.ox < 0 || h.ox >= h.Lx || h.t < 0 ||
-        h.cell_borders > OKPZ_CELLS_DELAYED)
+        h.cell_borders > OKPZ_CELLS_DELAYED || h.copies < 0 || h.copies > 2)
         return fail(OKPZ_EINVAL, "corrupt checkpoint header");
     const size_t pb = plane_bytes(h.Lx, h.Ly);
     if (bytes < sizeof h + pb) return fail(OKPZ_EINVAL, "checkpoint truncated");
     okpz_sim *s = nullptr;
-    int rc = make_sim(&s, h.Lx, h.Ly, h.p, h.q, h.seed, nullptr, 0, nullptr);
+    int rc = make_sim(&s, h.Lx, h.Ly, h.p, h.q, h.seed, nullptr, 0, nullptr, h.copies == 1 ? 1 : 2);
     if (rc != OKPZ_OK) return rc;
     hipError_t e = hipMemcpy(s->buf[0], static_cast<const char *>(buf) + sizeof h, pb,
                              hipMemcpyHostToDevice);

@@ -68,6 +68,11 @@ struct SweepLaunch {
     int32_t blk00, u00, v00;
     int32_t need_accept_draws;
     int32_t delayed_cells;  // 1: delayed thread-cell borders, 0: dead ones
+    int32_t in_place;       // 1: one lattice copy (src == dst), blocks stored back in place
+    // blocks of this launch: block columns col0 + i col_step, i < ncol, of
+    // every block row (launch_sweep sets them; blk00 is then numbered among
+    // them, -1 if the block holding site (0,0) is not one of them)
+    int32_t col0, col_step, ncol;
 };
 
 // Block shift of sweep s (host side; the kernel uses the same values).

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a, int G, i
     extern __shared__ __align__(16) uint8_t smem_dyn[];
     __shared__ __align__(16) uint8_t smem_fix[kFixedB ? (kFixedB + 1) * kFixedB : 16];
     __shared__ uint32_t opk_fix[kFixedB ? 32 : 1];
-    const int nblk = a.nbx * a.nby;
+    const int nblk = a.ncol * a.nby;
     const int nl = gridDim.x;  // groups of this launch, starting at group g0
     // XCD-aware order: consecutive workgroups are dealt round-robin to the 8
     // XCDs; give each XCD a contiguous run of groups so neighbouring blocks
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a, int G, i
 template <int kThreads, int kMode, int kFixedB>
 hipError_t launch_b(const SweepLaunch &a, hipStream_t st)
 {
-    const int nblk = a.nbx * a.nby;
+    const int nblk = a.ncol * a.nby;
     const int G = kFixedB ? 1 : core::group_size(a.Bx, a.By, nblk);
     const int ngroups = (nblk + G - 1) / G;
     const size_t lds = kFixedB ? 0
@@ -86,6 +86,10 @@ hipError_t launch_c(const SweepLaunch &a, hipStream_t st)
 template <int kThreads>
 hipError_t launch_t(const SweepLaunch &a, hipStream_t st)
 {
+    if (a.in_place) {
+        if (a.delayed_cells) return launch_c<kThreads, core::kDelayedCells | core::kInPlace>(a, st);
+        return launch_c<kThreads, core::kInPlace>(a, st);
+    }
     if (a.delayed_cells) return launch_c<kThreads, core::kDelayedCells>(a, st);
     return launch_c<kThreads, 0>(a, st);
 }
@@ -101,13 +105,46 @@ void block_shift(uint32_t k0, uint32_t k1, uint32_t s, const Geometry &g, int32_
 
 bool sweep_threads_ok(int threads) { return threads == 256 || threads == 512 || threads == 1024; }
 
-hipError_t launch_sweep(const SweepLaunch &a, int threads, hipStream_t st)
+namespace {
+
+hipError_t launch_threads(const SweepLaunch &a, int threads, hipStream_t st)
 {
     switch (threads) {
     case 256: return launch_t<256>(a, st);
     case 512: return launch_t<512>(a, st);
     default: return launch_t<1024>(a, st);
     }
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const SweepLaunch &a, int threads, hipStream_t st)
+{
+    SweepLaunch b = a;
+    if (!a.in_place || a.nbx == 1) {
+        b.col0 = 0;
+        b.col_step = 1;
+        b.ncol = a.nbx;
+        return launch_threads(b, threads, st);
+    }
+    // One copy updated in place: horizontally adjacent blocks share a word
+    // at either end of each row segment, so they go to different launches:
+    // even block columns, odd ones, and with an odd count the last column
+    // (the left neighbour of column 0) on its own.
+    const int odd = a.nbx & 1;
+    const int cls[3][3] = {{0, 2, a.nbx / 2}, {1, 2, a.nbx / 2}, {a.nbx - 1, 1, 1}};
+    const int bi00 = a.blk00 % a.nbx, bj00 = a.blk00 / a.nbx;
+    for (int c = 0; c < 2 + odd; ++c) {
+        b.col0 = cls[c][0];
+        b.col_step = cls[c][1];
+        b.ncol = cls[c][2];
+        const int i = bi00 - b.col0;
+        const bool mine = i >= 0 && i % b.col_step == 0 && i / b.col_step < b.ncol;
+        b.blk00 = mine ? bj00 * b.ncol + i / b.col_step : -1;
+        const hipError_t e = launch_threads(b, threads, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace okpz

@@ -53,8 +53,10 @@ constexpr int kGroupLds = 65536 + kMaxGroup * 32 + kMaxGroup * 32 * 4 + kMaxGrou
 // mode selects the delayed thread-cell borders of Sec. II: every cell draws
 // one of its 64 sites, and a step applies the attempts on cell-bulk sites,
 // then those on cell edges, then those on cell corners, with a barrier
-// after each phase.
-enum Mode : int { kGrowth = 0, kFixed = 1, kDraw = 2, kDelayedCells = 4 };
+// after each phase.  kInPlace added to a mode stores the blocks back into
+// the copy they were read from (one lattice copy; the launch holds no two
+// horizontally adjacent blocks).
+enum Mode : int { kGrowth = 0, kFixed = 1, kDraw = 2, kDelayedCells = 4, kInPlace = 8 };
 
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
 {
@@ -153,6 +155,13 @@ __device__ __forceinline__ bool move_accepted(uint32_t sv, uint32_t lv, uint32_t
     return (tbl >> code) & 1u;
 }
 
+// Set the bits of *w selected by mask to those of v and keep the others; the
+// caller guarantees that nobody else writes *w meanwhile.
+__device__ __forceinline__ void put_bits(uint32_t *w, uint32_t v, uint32_t mask)
+{
+    *w = (*w & ~mask) | (v & mask);
+}
+
 // LDS atomic XOR of one byte (a 32-bit atomic on the byte's word).
 __device__ __forceinline__ void xor_byte(uint8_t *smem, uint32_t off, uint32_t v)
 {
@@ -175,6 +184,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
 {
     constexpr int kMode = kModeFull & 3;
     constexpr bool kDelayed = (kModeFull & kDelayedCells) != 0;
+    constexpr bool kOneCopy = (kModeFull & kInPlace) != 0;
     constexpr bool kDrawAccept = (kMode == kDraw);
     constexpr int kCpt = kCellsMax / kThreads;
     if (kFixedB) {
@@ -192,22 +202,33 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     const int lcpb = ilog2((uint32_t)((Bx >> 3) * (By >> 3)));
     const int ncx = Bx >> 3;
 
+    // Block id of group member g.  Groups number the blocks of the launch:
+    // all blocks in row-major order, or, for a lattice updated in place, the
+    // blocks of the launch's block columns col0, col0 + col_step, ... (ncol
+    // of them per block row).
+    auto block_id = [&](int g) -> int {
+        const int l = b0 + g;
+        if (!kOneCopy) return l;
+        const int bj = l / a.ncol;
+        return bj * a.nbx + a.col0 + (l - bj * a.ncol) * a.col_step;
+    };
+
     // cell origins: one counter per pair of steps and block; word m of block
     // g holds steps 2m and 2m+1 (three bits per coordinate).
     for (int e = tid; e < G * (kSteps / 2); e += kThreads) {
         const int g = e >> 5, m = e & 31;
-        const Ctr4 r = philox10_dev(Ctr4{a.s, (uint32_t)(b0 + g), (uint32_t)m, kTagOrigin}, a.k0,
+        const Ctr4 r = philox10_dev(Ctr4{a.s, (uint32_t)block_id(g), (uint32_t)m, kTagOrigin}, a.k0,
                                     a.k1);
         opk[e] = (r.x >> 29) | ((r.y >> 29) << 3) | ((r.z >> 29) << 6) | ((r.w >> 29) << 9);
     }
 
     // ---- block placement -------------------------------------------------
-    // Block bid = b0 + g starts at lattice site (sx + bi Bx, sy + bj By); that
+    // Block bid = block_id(g) starts at lattice site (sx + bi Bx, sy + bj By); that
     // column sits at stored column xs of the source copy.  Per block: xs, the
     // first row and bi (the block's word column in the destination copy).
     const int lwpr = ilog2((uint32_t)wpr), lby = ilog2((uint32_t)By);
     auto place = [&](int g, int &xs, int &y0, int &bi) {
-        const int bid = b0 + g;
+        const int bid = block_id(g);
         bi = bid % a.nbx;
         const int bj = bid / a.nbx;
         xs = a.sx + bi * Bx - a.ox_src;
@@ -289,7 +310,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         const int c = q & ((1 << lcpb) - 1);
         const bool live = g < G;
         cid[j] = (uint32_t)c;
-        bidj[j] = (uint32_t)(b0 + (live ? g : 0));
+        bidj[j] = (uint32_t)block_id(live ? g : 0);
         // dead cell borders: the active sites start one in from the origin
         cxo[j] = (uint32_t)((c % ncx) * 8 + (kDelayed ? 0 : 1));
         cyo[j] = (uint32_t)((c / ncx) * 8 + (kDelayed ? 0 : 1));
@@ -493,6 +514,48 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             byw |= yb << (8 * b);
         }
         const size_t col = (size_t)bi * wpr + k;
+        if (kOneCopy) {
+            // One lattice copy: the block goes back where it was read from,
+            // its row segment starting at stored column xs (off = xs mod 32
+            // is the same for every block of the sweep).  Blocks cover
+            // disjoint sites and a block reads and writes only its own, so no
+            // block sees another's update.  Segment word k takes tile word k
+            // shifted up by off plus the top off bits of tile word k-1 (the
+            // previous lane's).  The segment's first and one-past-last words
+            // are shared with the left and right neighbour blocks, which the
+            // host never puts in the same launch, so a plain read-modify-write
+            // replaces only this block's bits.  With one block per row those
+            // two words are one word, all of it this block's: the first lane
+            // writes it whole, with the last lane's top bits.
+            const int xs = kFixedB ? fxs : geo[3 * g];
+            const uint32_t off = (uint32_t)(xs & 31);
+            const uint32_t nx = ~bxw, ny = ~byw;
+            const uint32_t px = __shfl_up(nx, 1, 64), py = __shfl_up(ny, 1, 64);
+            const uint32_t lx = __shfl_down(nx, wpr - 1, 64), ly = __shfl_down(ny, wpr - 1, 64);
+            uint32_t *rx = a.dst + (size_t)y * a.W, *ry = a.dst + ((size_t)a.Ly + y) * a.W;
+            int gw = (xs >> 5) + k;
+            if (gw >= a.W) gw -= a.W;
+            if (off == 0) {
+                rx[gw] = nx;
+                ry[gw] = ny;
+            } else if (k != 0) {
+                rx[gw] = (nx << off) | (px >> (32 - off));
+                ry[gw] = (ny << off) | (py >> (32 - off));
+            } else if (a.nbx == 1) {
+                rx[gw] = (nx << off) | (lx >> (32 - off));
+                ry[gw] = (ny << off) | (ly >> (32 - off));
+            } else {
+                put_bits(rx + gw, nx << off, ~0u << off);
+                put_bits(ry + gw, ny << off, ~0u << off);
+            }
+            if (k == wpr - 1 && off != 0 && a.nbx != 1) {
+                int gl = gw + 1;
+                if (gl == a.W) gl = 0;
+                put_bits(rx + gl, nx >> (32 - off), (1u << off) - 1u);
+                put_bits(ry + gl, ny >> (32 - off), (1u << off) - 1u);
+            }
+            continue;
+        }
         uint32_t *w0 = a.dst + (size_t)y * a.W + col, *w1 = a.dst + ((size_t)a.Ly + y) * a.W + col;
         if (kStoreThrough) {
             __hip_atomic_store(w0, ~bxw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);

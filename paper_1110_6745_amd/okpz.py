@@ -61,6 +61,10 @@ _sig("okpz_init", ctypes.c_int, ctypes.POINTER(_vp), _i64, _i64, ctypes.c_double
      ctypes.c_double, ctypes.c_uint64)
 _sig("okpz_init_on", ctypes.c_int, ctypes.POINTER(_vp), _i64, _i64, ctypes.c_double,
      ctypes.c_double, ctypes.c_uint64, _vp, _sz, _vp)
+_sig("okpz_required_bytes_in_place", _sz, _i64, _i64)
+_sig("okpz_init_in_place", ctypes.c_int, ctypes.POINTER(_vp), _i64, _i64, ctypes.c_double,
+     ctypes.c_double, ctypes.c_uint64, _vp, _sz, _vp)
+_sig("okpz_get_copies", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int32))
 _sig("okpz_sweep", ctypes.c_int, _vp, _i64)
 _sig("okpz_width", ctypes.c_int, _vp, _i64, _i64p, _i64p)
 _sig("okpz_w2", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double))
@@ -122,7 +126,8 @@ _sig("okpz_serve_stats", ctypes.c_int, _vp, _i64p, ctypes.POINTER(ctypes.c_doubl
      ctypes.POINTER(_sz))
 _sig("okpz_serve_free", ctypes.c_int, _vp)
 
-EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on", "okpz_sweep",
+EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
+            "okpz_required_bytes_in_place", "okpz_init_in_place", "okpz_get_copies", "okpz_sweep",
             "okpz_width", "okpz_w2", "okpz_psd", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
             "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads",
             "okpz_set_cell_borders", "okpz_get_cell_borders", "okpz_sync",
@@ -168,6 +173,19 @@ def okpz_init_on(Lx: int, Ly: int, p: float, q: float, seed: int, dev_ptr: int, 
     h = _vp()
     _check(_lib.okpz_init_on(ctypes.byref(h), Lx, Ly, float(p), float(q), int(seed),
                              _vp(dev_ptr), nbytes, _vp(stream_ptr or 0)))
+    return Sim(h, Lx, Ly)
+
+
+def okpz_required_bytes_in_place(Lx: int, Ly: int) -> int:
+    return int(_lib.okpz_required_bytes_in_place(Lx, Ly))
+
+
+def okpz_init_in_place(Lx: int, Ly: int, p: float, q: float, seed: int, dev_ptr: int = 0,
+                       nbytes: int = 0, stream_ptr: int | None = None) -> "Sim":
+    """One lattice copy updated in place (dev_ptr 0: the library allocates)."""
+    h = _vp()
+    _check(_lib.okpz_init_in_place(ctypes.byref(h), Lx, Ly, float(p), float(q), int(seed),
+                                   _vp(dev_ptr or 0), nbytes, _vp(stream_ptr or 0)))
     return Sim(h, Lx, Ly)
 
 
@@ -273,6 +291,11 @@ class Sim:
         k = ctypes.c_int32()
         _check(_lib.okpz_get_cell_borders(self._h, ctypes.byref(k)))
         return k.value
+
+    def copies(self) -> int:
+        c = ctypes.c_int32()
+        _check(_lib.okpz_get_copies(self._h, ctypes.byref(c)))
+        return c.value
 
     def sync(self) -> None:
         _check(_lib.okpz_sync(self._h))

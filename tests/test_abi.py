@@ -43,6 +43,29 @@ def test_required_bytes():
     assert okpz.okpz_required_bytes(33, 32) == 0
 
 
+def test_required_bytes_in_place():
+    from paper_1110_6745_amd import okpz
+
+    # one lattice copy: exactly one copy's bytes less than two copies, and the
+    # largest lattice, 2^20 x 2^20, within 256 GiB + 64 MiB
+    for Lx, Ly in [(32, 32), (96, 64), (2**17, 2**17), (2**20, 2**20)]:
+        one, two = okpz.okpz_required_bytes_in_place(Lx, Ly), okpz.okpz_required_bytes(Lx, Ly)
+        plane = -(-(Lx * Ly // 4) // 256) * 256
+        assert two - one == plane
+    assert okpz.okpz_required_bytes_in_place(2**20, 2**20) < 2**38 + 2**26
+    assert okpz.okpz_required_bytes_in_place(32, 48) == 0
+
+
+@pytest.mark.parametrize("Lx,Ly,p,q", [(33, 32, 1, 0), (32, 2**21, 1, 0), (32, 32, 0, 2.0)])
+def test_init_in_place_rejects_bad_arguments(Lx, Ly, p, q):
+    # rejected on the host before any device call
+    from paper_1110_6745_amd import okpz
+
+    with pytest.raises(okpz.OkpzError) as e:
+        okpz.okpz_init_in_place(Lx, Ly, p, q, 1)
+    assert e.value.code == okpz.OKPZ_EINVAL
+
+
 @pytest.mark.parametrize("Lx,Ly,p,q", [(33, 32, 1, 0), (32, 16, 1, 0), (0, 32, 1, 0),
                                         (2**21, 32, 1, 0), (32, 32, 1.5, 0), (32, 32, 0, -0.1),
                                         (32, 32, float("nan"), 0)])
