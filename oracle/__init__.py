@@ -2,7 +2,7 @@
 
 Plain CPU reference of the octahedron-model hot path (Kelling & Odor,
 arXiv:1110.6745): the seeded tiled dynamics of Sec. II, the textbook
-random-sequential judge, height reconstruction (Sec. I) and the exact width
+random-sequential reference, height reconstruction (Sec. I) and the exact width
 sums of Eq. (Wdef).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
 code with the HIP library (``paper_1110_6745_amd``) and never imports it.
@@ -205,7 +205,7 @@ def block_sweep(blk: np.ndarray, C: int, seed: int, s: int, block_id: int, p: fl
 
 def rsu_sweep(lat: np.ndarray, p: float, q: float, seed: int, t: int, H0: int,
               counts: Counts | None = None) -> int:
-    """One MCS (N attempts) of the random-sequential judge; returns new H0."""
+    """One MCS (N attempts) of the random-sequential reference; returns new H0."""
     _check_lattice(lat)
     Ly, Lx = lat.shape
     h = ctypes.c_int64(H0)
@@ -254,7 +254,7 @@ def ensemble(Lx: int, Ly: int, p: float, q: float, seed0: int, R: int, tmax: int
              rsu: bool = False, delayed: bool = False) -> np.ndarray:
     """(S1, S2) after every MCS t = 1..tmax of R flat-start realizations with
     seeds seed0 .. seed0+R-1; returns an int64 array of shape (R, tmax, 2).
-    ``rsu`` selects the random-sequential judge, ``delayed`` the tiled
+    ``rsu`` selects the random-sequential reference, ``delayed`` the tiled
     dynamics with delayed cell borders."""
     out = np.zeros((R, tmax, 2), dtype=np.int64)
     kind = 1 if rsu else (2 if delayed else 0)

@@ -315,7 +315,7 @@ int or_sweep(uint8_t *lat, int64_t Lx, int64_t Ly, uint64_t Tp, uint64_t Tq,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Textbook random-sequential update (statistical judge): one MCS of sweep   */
+/* Textbook random-sequential update (statistical reference): one MCS of sweep   */
 /* index t is N = Lx*Ly attempts ("one overall update", Sec. II); attempt n  */
 /* picks a uniform site and applies Eq. (1).  Attempt a = t*N + n uses       */
 /* counter (a mod 2^32, a / 2^32, 0, RSU): x from word 0, y from word 1,     */
@@ -416,7 +416,7 @@ void or_set_num_threads(int n)
 /* Ensemble driver for the statistical pins: R independent realizations     */
 /* (seed0 + r) from the flat state; after each MCS t = 1..tmax, stores      */
 /* (S1, S2) into out[(r*tmax + t-1)*2 + {0,1}].  kind: 0 the tiled dynamics */
-/* with dead cell borders, 1 the random-sequential judge, 2 the tiled        */
+/* with dead cell borders, 1 the random-sequential reference, 2 the tiled        */
 /* dynamics with delayed cell borders.                                       */
 /* ------------------------------------------------------------------------ */
 int or_ensemble(int64_t Lx, int64_t Ly, double p, double q, uint64_t seed0, int64_t R,

@@ -23,7 +23,7 @@ SHAPES_GPU = [(32, 32), (64, 32), (96, 96), (256, 256), (320, 192), (512, 1024),
 
 def rough_state(Lx, Ly, seed, mcs=3, p=0.7, q=0.4):
     """A valid non-flat slope field: the flat state evolved by the oracle's
-    random-sequential judge for a few MCS.  Returns (lattice, H0)."""
+    random-sequential reference for a few MCS.  Returns (lattice, H0)."""
     import oracle
 
     lat = oracle.flat(Lx, Ly)

@@ -142,7 +142,7 @@ def test_full_size_one_sweep_on_sampled_blocks(okpz):
 def test_growth_width_against_random_sequential(okpz):
     """Sec. II expects the decomposition to change prefactors at most, not
     exponents: the excess width W^2 - 1/4 of both border contracts (GPU) and
-    of the random-sequential judge (oracle) during growth, averaged over
+    of the random-sequential reference (oracle) during growth, averaged over
     seeds, agree within their statistical errors.  Prints the table."""
     L, R, p, q = 256, 12, 1.0, 0.0
     times = [10, 30, 100, 200]

@@ -6,7 +6,7 @@ stochasticity, the flat-state width 1/4 (Sec. III) and, for p = q, the
 closed-form stationary law: Eq. (1) with p = q is symmetric, so the chain is
 doubly stochastic and its stationary law is uniform over all states.  The C
 oracle's Monte Carlo histograms of W^2(t) (tiled dynamics and
-random-sequential judge) must then match the exact laws.
+random-sequential reference) must then match the exact laws.
 """
 from fractions import Fraction
 

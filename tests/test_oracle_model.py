@@ -136,7 +136,7 @@ def test_mirror_symmetry_bit_for_bit(p, q):
     S1, S2 = oracle.width_sums(lat, Ha)
     T1, T2 = oracle.width_sums(mir, Hb)
     assert T1 == -S1 and T2 == S2
-    # the random-sequential judge has the same symmetry
+    # the random-sequential reference has the same symmetry
     lat2, H2 = inputs.rough_state(16, 16, seed=6)
     mir2 = (lat2 ^ 3).astype(np.uint8)
     Ha = oracle.rsu_run(lat2, p, q, 8, 0, 3, H2)
@@ -195,7 +195,7 @@ def test_no_bond_conflicts(Lx, Ly):
 def test_attempt_rate_per_mcs():
     """With p = q = 1 every eligible attempt flips.  Per MCS the tiled
     schedule attempts N sites minus the block borders (about 2/B of them);
-    its flip count must be close to the random-sequential judge's on the
+    its flip count must be close to the random-sequential reference's on the
     same state (the paper's border no-ops only change prefactors, Sec. II)."""
     Lx = Ly = 256
     lat, H0 = inputs.rough_state(Lx, Ly, seed=1, mcs=2)
