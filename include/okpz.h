@@ -277,6 +277,12 @@ typedef struct okpz_server okpz_server; /* opaque */
 int okpz_serve_create(okpz_server **out, size_t hbm_budget, int32_t max_slots,
                       int64_t quantum_sites, double m);
 int okpz_serve_set_mapping(okpz_server *sv, int32_t threads, int32_t workgroups);
+/* Thread-cell borders (OKPZ_CELLS_DEAD, the default, or OKPZ_CELLS_DELAYED,
+ * Sec. II) of every job of the server; set before the first okpz_serve_submit
+ * (OKPZ_EINVAL afterwards).  Each job's result is then that of a lone
+ * simulation with the same borders. */
+int okpz_serve_set_cell_borders(okpz_server *sv, int32_t kind);
+int okpz_serve_get_cell_borders(const okpz_server *sv, int32_t *kind);
 /* Seconds since the server was created. */
 int okpz_serve_now(okpz_server *sv, double *now);
 /* Queue a job; OKPZ_EBUSY if it could never fit the budget.  keep_lattice:

@@ -1038,6 +1038,7 @@ struct okpz_server {
     hipStream_t stream = nullptr;
     hipStream_t grid_stream = nullptr;  // plain sweeps of large lattices
     int threads = 512, wgs = 0, cus = 0;  // two workgroups per CU without spills
+    int32_t cell_borders = OKPZ_CELLS_DEAD;  // for every job of the server
     std::chrono::steady_clock::time_point t0;
     int64_t quanta = 0, done = 0;
     double device_ms = 0;
@@ -1169,6 +1170,7 @@ int run_grid(okpz_server *sv, ServeJob &J, int64_t stop)
     a.Tp = d.Tp;
     a.Tq = d.Tq;
     a.need_accept_draws = d.mode == okpz::core::kDraw ? 1 : 0;
+    a.delayed_cells = sv->cell_borders == OKPZ_CELLS_DELAYED ? 1 : 0;
     while (J.s < stop) {
         const uint32_t sw = (uint32_t)J.s;
         int32_t sx, sy;
@@ -1263,6 +1265,23 @@ int okpz_serve_set_mapping(okpz_server *sv, int32_t threads, int32_t workgroups)
     if (workgroups < 0 || workgroups > (1 << 16)) return bfail(OKPZ_EINVAL, "workgroups out of range");
     sv->threads = threads;
     sv->wgs = workgroups;
+    return OKPZ_OK;
+}
+
+int okpz_serve_set_cell_borders(okpz_server *sv, int32_t kind)
+{
+    if (!sv) return bfail(OKPZ_EINVAL, "null server");
+    if (kind != OKPZ_CELLS_DEAD && kind != OKPZ_CELLS_DELAYED)
+        return bfail(OKPZ_EINVAL, "cell border kind %d is neither dead (0) nor delayed (1)", kind);
+    if (!sv->jobs.empty()) return bfail(OKPZ_EINVAL, "cell borders are set before the first submit");
+    sv->cell_borders = kind;
+    return OKPZ_OK;
+}
+
+int okpz_serve_get_cell_borders(const okpz_server *sv, int32_t *kind)
+{
+    if (!sv || !kind) return bfail(OKPZ_EINVAL, "null argument");
+    *kind = sv->cell_borders;
     return OKPZ_OK;
 }
 
@@ -1376,7 +1395,7 @@ int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting)
     BHIP(hipEventCreate(&eg));
     BHIP(hipEventRecord(e0, sv->stream));
     const Ring R{sv->d_desc, sv->d_state, sv->d_ctl, sv->d_claim, sv->d_sched, sv->max_slots,
-                 sv->stream, 0};
+                 sv->stream, sv->cell_borders == OKPZ_CELLS_DELAYED ? 1 : 0};
     if (n_small > 0) {
         Control ctl{};
         ctl.finished = finished;

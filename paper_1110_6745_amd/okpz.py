@@ -115,6 +115,8 @@ _sig("okpz_batch_last_error", ctypes.c_char_p)
 _sig("okpz_serve_create", ctypes.c_int, ctypes.POINTER(_vp), _sz, ctypes.c_int32, _i64,
      ctypes.c_double)
 _sig("okpz_serve_set_mapping", ctypes.c_int, _vp, ctypes.c_int32, ctypes.c_int32)
+_sig("okpz_serve_set_cell_borders", ctypes.c_int, _vp, ctypes.c_int32)
+_sig("okpz_serve_get_cell_borders", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int32))
 _sig("okpz_serve_now", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double))
 _sig("okpz_serve_submit", ctypes.c_int, _vp, _jobp, ctypes.c_double, ctypes.c_int32, _i64p)
 _sig("okpz_serve_step", ctypes.c_int, _vp, _i32p, _i32p)
@@ -136,7 +138,8 @@ EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_batch_get_cell_borders", "okpz_batch_autotune", "okpz_batch_run",
             "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
             "okpz_batch_w2_histogram", "okpz_batch_w2_cumulants", "okpz_batch_psi",
-            "okpz_serve_create", "okpz_serve_set_mapping",
+            "okpz_serve_create", "okpz_serve_set_mapping", "okpz_serve_set_cell_borders",
+            "okpz_serve_get_cell_borders",
             "okpz_serve_now", "okpz_serve_submit", "okpz_serve_step", "okpz_serve_job",
             "okpz_serve_samples", "okpz_serve_result", "okpz_serve_stats", "okpz_serve_free",
             "okpz_batch_free", "okpz_batch_last_error"]
@@ -456,6 +459,15 @@ class Server:
 
     def set_mapping(self, threads: int, workgroups: int = 0) -> None:
         _bcheck(_lib.okpz_serve_set_mapping(self._h, int(threads), int(workgroups)))
+
+    def set_cell_borders(self, kind: int) -> None:
+        """OKPZ_CELLS_DEAD (default) or OKPZ_CELLS_DELAYED, before the first submit."""
+        _bcheck(_lib.okpz_serve_set_cell_borders(self._h, int(kind)))
+
+    def cell_borders(self) -> int:
+        k = ctypes.c_int32()
+        _bcheck(_lib.okpz_serve_get_cell_borders(self._h, ctypes.byref(k)))
+        return k.value
 
     def now(self) -> float:
         v = ctypes.c_double()

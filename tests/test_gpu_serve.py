@@ -105,3 +105,33 @@ def test_poisson_stream_small(okpz):
     lat = [sv.job(i)["finish"] - sv.job(i)["arrival"] for i in ids]
     assert min(lat) >= 0
     sv.free()
+
+
+def test_delayed_borders_equal_alone(okpz):
+    # a server whose jobs run the delayed thread-cell borders: small jobs in
+    # the persistent launch, a 4096^2 one on plain sweeps, each equal to a
+    # lone delayed-border simulation
+    m = 0.3
+    jobs = [(64, 64, 1.0, 0.0, 61, 30), (256, 256, 0.95, 0.05, 62, 20), (96, 96, 0.7, 0.3, 63, 25),
+            (4096, 4096, 1.0, 0.0, 64, 5), (32, 64, 0.5, 0.5, 65, 40)]
+    sv = okpz.Server(hbm_budget=1 << 31, max_slots=3, quantum_sites=1 << 26, m=m)
+    assert sv.cell_borders() == okpz.OKPZ_CELLS_DEAD
+    sv.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
+    assert sv.cell_borders() == okpz.OKPZ_CELLS_DELAYED
+    ids = [sv.submit(j, arrival=0.001 * k, keep_lattice=True) for k, j in enumerate(jobs)]
+    with pytest.raises(okpz.OkpzError) as e:
+        sv.set_cell_borders(okpz.OKPZ_CELLS_DEAD)
+    assert e.value.code == okpz.OKPZ_EINVAL
+    sv.drain()
+    assert sv.stats()["done"] == len(jobs)
+    for i, job in zip(ids, jobs):
+        Lx, Ly, p, q, seed, t_max = job
+        sim = okpz.okpz_init(Lx, Ly, p, q, seed)
+        sim.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
+        ref = [(t,) + sim.width(t) for t in okpz.sampling_times(t_max, m)]
+        t, s1, s2 = sv.samples(i)
+        assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref, f"job {job}"
+        got, gh0 = sv.result(i, lattice=True)
+        assert np.array_equal(got, sim.get_lattice()) and gh0 == sim.h0(), f"job {job}"
+        sim.free()
+    sv.free()
