@@ -28,6 +28,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # (profiles/sweep_kernel_L131072_hbm_counters.md).  Reported only while the
 # sweep sources hash to the value the counters were taken on.
 TRAFFIC_MEASURED = {"sources_sha256_16": "6a92783189a6ae65", "L": 1 << 17, "bytes": 8.625e9}
+# VALU issue per site update of the growth sweep from rocprofv3 SQ_INSTS_VALU
+# and SQ_INSTS_VALU_INT64 (profiles/sweep_kernel_L131072_sq_counters.md): 22.3
+# wave instructions per 64 updates plus 2.8 for the second issue cycle of the
+# 64-bit multiplies.  Against 256 CUs x 64 lanes x 2.4 GHz of 32-bit lanes
+# this gives the ALU ceiling of the sweep; same source key as the traffic.
+VALU_MEASURED = {"sources_sha256_16": "6a92783189a6ae65", "lane_ops_per_update": 25.1}
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T 32-bit lane operations/s
 SWEEP_SOURCES = ("sweep_core.h", "sweep.hip", "okpz_internal.h")
 METRIC = "site updates/s (+% HBM roofline) at L=2^17; realizations/s batched vs plain; serving p50/p99"
 
@@ -302,9 +309,17 @@ def main():
     achieved_gbs = 0.5 * N / (sweep_ms * 1e-3) / 1e9
     w2 = [(t, (N * s2 - s1 * s1) / (N * N)) for t, s1, s2 in widths]
     traffic = None
+    src_key = sweep_sources_hash()
     if (L == TRAFFIC_MEASURED["L"] and not args.in_place
-            and sweep_sources_hash() == TRAFFIC_MEASURED["sources_sha256_16"]):
+            and src_key == TRAFFIC_MEASURED["sources_sha256_16"]):
         traffic = TRAFFIC_MEASURED["bytes"]
+    alu = None
+    if (args.cell_borders == "dead" and not args.in_place and args.threads == 1024
+            and src_key == VALU_MEASURED["sources_sha256_16"]):
+        ops = N / (sweep_ms * 1e-3) * VALU_MEASURED["lane_ops_per_update"] / 1e12
+        alu = {"bound": "alu", "achieved": ops, "peak": ALU_PEAK_TOPS, "unit": "T lane-ops/s",
+               "frac": ops / ALU_PEAK_TOPS,
+               "lane_ops_per_update": VALU_MEASURED["lane_ops_per_update"]}
 
     out = {
         "metric": METRIC,
@@ -329,6 +344,7 @@ def main():
         "sweep_site_updates_per_s": N / (sweep_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
+        "alu_ceiling": alu,
         "w2_last": w2[-1] if w2 else None,
     }
     if args.psd_calls > 0 and L & (L - 1) == 0:
