@@ -406,7 +406,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             // Philox call, pinned here so that it is not sunk to its use.
             // It is filler work: at low wave priority, so that waves whose
             // step chain can go on (towards the step barrier) issue first.
-            if (!kDelayed) __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_s_setprio(0);
             if (gs + 1 < kSteps / 8) {
 #pragma unroll
                 for (int j = 0; j < kCpt; ++j) {
@@ -423,7 +423,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                     asm volatile("" : "+v"(nxt[j].x), "+v"(nxt[j].y), "+v"(nxt[j].z), "+v"(nxt[j].w));
                 }
             }
-            if (!kDelayed) __builtin_amdgcn_s_setprio(2);
+            __builtin_amdgcn_s_setprio(2);
             if (kDelayed) {
                 // Three phases.  Within one, attempted sites are never nearest
                 // neighbours.  Bulk sites are not diagonal neighbours either
