@@ -490,6 +490,10 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         }
     }
 
+    // the store below is not on any step's critical path: back to low
+    // priority, behind the steps of a co-resident workgroup
+    __builtin_amdgcn_s_setprio(0);
+
     if (has00 && tid == 0) {
         const int post00 = row_prefix_bx(smem + g00 * tsz + (a.v00 + 1) * Bx, a.u00);
         *a.h0 += 2 * (int64_t)(post00 - pre00);
