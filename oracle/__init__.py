@@ -79,6 +79,20 @@ def lib() -> ctypes.CDLL:
                               ctypes.c_double, ctypes.c_uint64, ctypes.c_int64,
                               ctypes.c_int64, ctypes.c_int, _i64p]
     L.or_ensemble.restype = ctypes.c_int
+    L.or_ensemble_at.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _i64p,
+                                 ctypes.c_int64, ctypes.c_int, _i64p]
+    L.or_ensemble_at.restype = ctypes.c_int
+    L.or_window_sweep.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_uint32, _i64p, _i64p, _i64p, _i64p, _i64p,
+                                  ctypes.c_int]
+    L.or_window_sweep.restype = ctypes.c_int
+    L.or_width_rows.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_uint64), _i64p,
+                                ctypes.POINTER(ctypes.c_uint64), _i64p, _i64p]
+    L.or_width_rows.restype = None
     L.or_num_threads.argtypes = []
     L.or_num_threads.restype = ctypes.c_int
     L.or_set_num_threads.argtypes = [ctypes.c_int]
@@ -245,6 +259,20 @@ def width_sums(lat: np.ndarray, H0: int) -> tuple:
     return s1.value, s2.value
 
 
+def width_rows(rows: np.ndarray, h_start: int) -> tuple:
+    """(S1, S2, h_next) of a band of rows of a larger lattice whose first site
+    has height ``h_start``; exact Python integers (no int64 limit).  Summing
+    the bands of a lattice in order, each started at the previous band's
+    ``h_next`` (the first at H0), gives ``width_sums`` of the whole lattice."""
+    _check_lattice(rows)
+    n, Lx = rows.shape
+    s1l, s2l = ctypes.c_uint64(), ctypes.c_uint64()
+    s1h, s2h, hn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    lib().or_width_rows(_ptr(rows, _u8p), Lx, n, int(h_start), ctypes.byref(s1l),
+                        ctypes.byref(s1h), ctypes.byref(s2l), ctypes.byref(s2h), ctypes.byref(hn))
+    return (s1h.value << 64) + s1l.value, (s2h.value << 64) + s2l.value, hn.value
+
+
 def w2(S1: int, S2: int, N: int) -> float:
     """W^2 = S2/N - (S1/N)^2 from exact sums (numerator in Python integers)."""
     return (N * S2 - S1 * S1) / (N * N)
@@ -256,12 +284,77 @@ def ensemble(Lx: int, Ly: int, p: float, q: float, seed0: int, R: int, tmax: int
     seeds seed0 .. seed0+R-1; returns an int64 array of shape (R, tmax, 2).
     ``rsu`` selects the random-sequential reference, ``delayed`` the tiled
     dynamics with delayed cell borders."""
-    out = np.zeros((R, tmax, 2), dtype=np.int64)
+    return ensemble_at(Lx, Ly, p, q, seed0, R, list(range(1, tmax + 1)), rsu, delayed)
+
+
+def ensemble_at(Lx: int, Ly: int, p: float, q: float, seed0: int, R: int, times,
+                rsu: bool = False, delayed: bool = False) -> np.ndarray:
+    """(S1, S2) after MCS ``times`` (increasing, >= 1) of R flat-start
+    realizations with seeds seed0 .. seed0+R-1, realizations spread over the
+    host threads; an int64 array of shape (R, len(times), 2)."""
+    tv = np.ascontiguousarray(np.asarray(times, dtype=np.int64))
+    out = np.zeros((R, len(tv), 2), dtype=np.int64)
     kind = 1 if rsu else (2 if delayed else 0)
-    rc = lib().or_ensemble(Lx, Ly, float(p), float(q), seed0, R, tmax, kind,
-                           _ptr(out, _i64p))
+    rc = lib().or_ensemble_at(Lx, Ly, float(p), float(q), seed0, R, _ptr(tv, _i64p), len(tv),
+                              kind, _ptr(out, _i64p))
     if rc != 0:
-        raise RuntimeError(f"or_ensemble failed ({rc})")
+        raise RuntimeError(f"or_ensemble_at failed ({rc})")
+    return out
+
+
+class Window:
+    """The exact state of a rectangle of a large periodic lattice under the
+    tiled dynamics (blocks of a sweep are independent, Sec. II).
+
+    ``lat`` holds lattice sites ((wx0 + u) mod Lx, (wy0 + v) mod Ly) at
+    ``lat[v, u]``; ``valid`` = (vx0, vy0, vx1, vy1) is the half-open rectangle
+    of window coordinates whose state is exact; ``H0`` is the height of site
+    (0,0) while it stays inside.  Each ``sweep`` updates the blocks lying
+    wholly inside ``valid`` and shrinks it to their union."""
+
+    def __init__(self, lat: np.ndarray, wx0: int, wy0: int, Lx: int, Ly: int, H0: int = 0):
+        _check_lattice(lat)
+        self.lat, self.wx0, self.wy0, self.Lx, self.Ly, self.H0 = lat, wx0, wy0, Lx, Ly, H0
+        self.valid = (0, 0, lat.shape[1], lat.shape[0])
+
+    def sweep(self, p: float, q: float, seed: int, s: int, delayed: bool = False) -> None:
+        Wy, Wx = self.lat.shape
+        v = [ctypes.c_int64(x) for x in self.valid]
+        h = ctypes.c_int64(self.H0)
+        rc = lib().or_window_sweep(_ptr(self.lat, _u8p), Wx, Wy, self.wx0, self.wy0, self.Lx,
+                                   self.Ly, threshold(p), threshold(q), seed, s,
+                                   ctypes.byref(v[0]), ctypes.byref(v[1]), ctypes.byref(v[2]),
+                                   ctypes.byref(v[3]), ctypes.byref(h), int(delayed))
+        if rc != 0:
+            raise ValueError(f"or_window_sweep failed ({rc})")
+        self.valid = tuple(x.value for x in v)
+        self.H0 = h.value
+
+
+def flat_window(wx0: int, wy0: int, Wx: int, Wy: int) -> np.ndarray:
+    """Sites ((wx0 + u), (wy0 + v)) of the flat zig-zag state (Sec. III) of
+    any even-sided periodic lattice: bx = by = [x + y even]."""
+    x = (wx0 + np.arange(Wx)) % 2
+    y = (wy0 + np.arange(Wy)) % 2
+    up = ((x[None, :] + y[:, None]) % 2 == 0).astype(np.uint8)
+    return np.ascontiguousarray(up | (up << 1))
+
+
+def sampling_times(t_max: int, m: float) -> list:
+    """Measurement times of Sec. III: t_{i+1} = (t_i + 10) e^m from t_0 = 0,
+    each rounded up to a whole MCS, repeats dropped, and t_max itself last."""
+    import math
+
+    out, t = [], 0.0
+    while True:
+        t = (t + 10.0) * math.exp(m)
+        if t > t_max:
+            break
+        c = math.ceil(t)
+        if c not in out:
+            out.append(c)
+    if t_max > 0 and t_max not in out:
+        out.append(t_max)
     return out
 
 

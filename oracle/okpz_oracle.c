@@ -390,6 +390,50 @@ int or_width(const uint8_t *lat, int64_t Lx, int64_t Ly, int64_t H0,
     return 0;
 }
 
+/* S1 and S2 of a band of nrows consecutive rows of a larger lattice, given  */
+/* the height h_start of the band's first site (column 0 of its first row): */
+/* the same sums as or_width, for a lattice streamed band by band.  Row y of */
+/* the band starts at h_start + sum_{k<y} sigma_y(0,k) (column 0 of the band */
+/* rows above); the sums come back as 128-bit integers split into a low and */
+/* a high 64-bit word (value = hi * 2^64 + lo), and *h_next receives the     */
+/* start height of the row after the band.  Rows are summed on host threads. */
+void or_width_rows(const uint8_t *rows, int64_t Lx, int64_t nrows, int64_t h_start,
+                   uint64_t *s1_lo, int64_t *s1_hi, uint64_t *s2_lo, int64_t *s2_hi,
+                   int64_t *h_next)
+{
+    int64_t *start = (int64_t *)malloc((size_t)(nrows > 0 ? nrows : 1) * sizeof(int64_t));
+    int64_t col = h_start;
+    for (int64_t y = 0; y < nrows; ++y) {
+        start[y] = col;
+        col += bit_to_slope((rows[y * Lx + 0] >> 1) & 1);
+    }
+    *h_next = col;
+    __int128 s1 = 0, s2 = 0;
+#pragma omp parallel
+    {
+        __int128 a1 = 0, a2 = 0;
+#pragma omp for schedule(static)
+        for (int64_t y = 0; y < nrows; ++y) {
+            int64_t hv = start[y];
+            for (int64_t x = 0; x < Lx; ++x) {
+                a1 += hv;
+                a2 += (__int128)hv * hv;
+                hv += bit_to_slope(rows[y * Lx + x] & 1);
+            }
+        }
+#pragma omp critical
+        {
+            s1 += a1;
+            s2 += a2;
+        }
+    }
+    free(start);
+    *s1_lo = (uint64_t)s1;
+    *s1_hi = (int64_t)(s1 >> 64);
+    *s2_lo = (uint64_t)s2;
+    *s2_hi = (int64_t)(s2 >> 64);
+}
+
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -413,33 +457,135 @@ void or_set_num_threads(int n)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Ensemble driver for the statistical pins: R independent realizations     */
-/* (seed0 + r) from the flat state; after each MCS t = 1..tmax, stores      */
-/* (S1, S2) into out[(r*tmax + t-1)*2 + {0,1}].  kind: 0 the tiled dynamics */
-/* with dead cell borders, 1 the random-sequential reference, 2 the tiled        */
-/* dynamics with delayed cell borders.                                       */
+/* Ensemble driver for the statistical pins and the random-sequential        */
+/* reference of the beta comparison: R independent realizations (seed0 + r)  */
+/* from the flat state (Sec. III); after MCS times[i] (strictly increasing,  */
+/* >= 1) stores (S1, S2) into out[(r*ntimes + i)*2 + {0,1}].  kind: 0 the     */
+/* tiled dynamics with dead cell borders, 1 the random-sequential reference, */
+/* 2 the tiled dynamics with delayed cell borders.  Realizations run on      */
+/* separate host threads (each realization itself is the plain serial code; */
+/* the block loop inside or_sweep then runs on one thread).                  */
+/* Returns 0, -1 on a bond conflict, -2 on bad arguments or memory, -3 if a  */
+/* width sum leaves int64.                                                   */
 /* ------------------------------------------------------------------------ */
+int or_ensemble_at(int64_t Lx, int64_t Ly, double p, double q, uint64_t seed0, int64_t R,
+                   const int64_t *times, int64_t ntimes, int kind, int64_t *out)
+{
+    const uint64_t Tp = or_threshold(p), Tq = or_threshold(q);
+    for (int64_t i = 0; i < ntimes; ++i)
+        if (times[i] < 1 || (i > 0 && times[i] <= times[i - 1])) return -2;
+    int rc = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : rc) if (R > 1)
+    for (int64_t r = 0; r < R; ++r) {
+        int e = 0; /* this realization's status */
+        uint8_t *lat = (uint8_t *)malloc((size_t)(Lx * Ly));
+        if (!lat) e = -2;
+        else or_flat(lat, Lx, Ly);
+        int64_t H0 = 0, t = 0;
+        for (int64_t i = 0; i < ntimes && e == 0; ++i) {
+            for (; t < times[i] && e == 0; ++t) {
+                if (kind == 1)
+                    or_rsu_sweep(lat, Lx, Ly, Tp, Tq, seed0 + (uint64_t)r, (uint64_t)t, &H0,
+                                 NULL, NULL);
+                else if (or_sweep(lat, Lx, Ly, Tp, Tq, seed0 + (uint64_t)r, (uint32_t)t, &H0,
+                                  NULL, NULL, 0, kind == 2) != 0)
+                    e = -1;
+            }
+            if (e != 0) break;
+            int64_t *o = &out[(r * ntimes + i) * 2];
+            if (or_width(lat, Lx, Ly, H0, &o[0], &o[1]) != 0) e = -3;
+        }
+        free(lat);
+        if (e < rc) rc = e; /* the reduction's private copy starts at INT_MAX */
+    }
+    return rc;
+}
+
+/* (S1, S2) after every MCS t = 1..tmax: or_ensemble_at with times 1..tmax. */
 int or_ensemble(int64_t Lx, int64_t Ly, double p, double q, uint64_t seed0, int64_t R,
                 int64_t tmax, int kind, int64_t *out)
 {
-    const uint64_t Tp = or_threshold(p), Tq = or_threshold(q);
-    uint8_t *lat = (uint8_t *)malloc((size_t)(Lx * Ly));
-    if (!lat) return -2;
-    for (int64_t r = 0; r < R; ++r) {
-        or_flat(lat, Lx, Ly);
-        int64_t H0 = 0;
-        for (int64_t t = 0; t < tmax; ++t) {
-            if (kind == 1) {
-                or_rsu_sweep(lat, Lx, Ly, Tp, Tq, seed0 + (uint64_t)r, (uint64_t)t, &H0, NULL, NULL);
-            } else if (or_sweep(lat, Lx, Ly, Tp, Tq, seed0 + (uint64_t)r, (uint32_t)t, &H0, NULL,
-                                NULL, 0, kind == 2) != 0) {
-                free(lat);
-                return -1;
-            }
-            int64_t *o = &out[(r * tmax + t) * 2];
-            if (or_width(lat, Lx, Ly, H0, &o[0], &o[1]) != 0) { free(lat); return -3; }
-        }
+    int64_t *times = (int64_t *)malloc((size_t)(tmax > 0 ? tmax : 1) * sizeof(int64_t));
+    if (!times) return -2;
+    for (int64_t t = 0; t < tmax; ++t) times[t] = t + 1;
+    int rc = or_ensemble_at(Lx, Ly, p, q, seed0, R, times, tmax, kind, out);
+    free(times);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The tiled dynamics on a window of a larger periodic lattice.  Blocks of a */
+/* sweep are independent (Sec. II), so the sites of one block after sweep s  */
+/* depend only on that block's sites before it.  Given the exact state of a  */
+/* rectangle of the Lx x Ly lattice, a sweep can therefore be applied        */
+/* exactly to every block of the sweep's decomposition that lies wholly      */
+/* inside the rectangle; the union of those blocks is again a rectangle and  */
+/* is where the state is known exactly afterwards.  Starting from a large    */
+/* enough rectangle of the flat state, this gives the exact state of any     */
+/* part of a lattice far too large to hold, after a few sweeps.              */
+/*                                                                          */
+/* win: Wx*Wy bytes, win[v*Wx + u] is lattice site ((wx0 + u) mod Lx,        */
+/*      (wy0 + v) mod Ly).                                                   */
+/* *vx0, *vy0, *vx1, *vy1 (window coordinates, half-open): the rectangle     */
+/*      known exactly before the sweep; replaced by the one known after it   */
+/*      (empty, vx1 <= vx0, when no block fits).                             */
+/* *H0: when lattice site (0,0) lies in a processed block, its height change */
+/*      is added (the caller knows whether (0,0) stays inside).              */
+/* Needs Wx <= Lx and Wy <= Ly, so a lattice site appears at most once.     */
+/* Returns 0, -1 on a bond conflict, -2 on bad arguments.                    */
+/* ------------------------------------------------------------------------ */
+static int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+int or_window_sweep(uint8_t *win, int64_t Wx, int64_t Wy, int64_t wx0, int64_t wy0,
+                    int64_t Lx, int64_t Ly, uint64_t Tp, uint64_t Tq, uint64_t seed,
+                    uint32_t s, int64_t *vx0, int64_t *vy0, int64_t *vx1, int64_t *vy1,
+                    int64_t *H0, int delayed)
+{
+    int32_t Bx, By, C;
+    if (or_geometry(Lx, Ly, &Bx, &By, &C) != 0 || Wx > Lx || Wy > Ly) return -2;
+    int32_t sx, sy;
+    or_block_shift(seed, s, Bx, By, &sx, &sy);
+    const int64_t nbx = Lx / Bx, nby = Ly / By;
+    /* lattice x of window column u is wx0 + u (unwrapped); block column i
+     * starts at sx + i*Bx, taken in unwrapped coordinates: the first block
+     * starting at or after wx0 + vx0 and the last one ending by wx0 + vx1 */
+    const int64_t ax = wx0 + *vx0, bxe = wx0 + *vx1, ay = wy0 + *vy0, bye = wy0 + *vy1;
+    const int64_t i0 = floor_div(ax - sx + Bx - 1, Bx), i1 = floor_div(bxe - sx, Bx);
+    const int64_t j0 = floor_div(ay - sy + By - 1, By), j1 = floor_div(bye - sy, By);
+    if (i1 <= i0 || j1 <= j0) {
+        *vx1 = *vx0;
+        *vy1 = *vy0;
+        return 0;
     }
-    free(lat);
-    return 0;
+    int bad = 0;
+    int64_t dh = 0;
+    const int64_t ni = i1 - i0, nblk = ni * (j1 - j0);
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : dh) reduction(| : bad)
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t i = i0 + b % ni, j = j0 + b / ni;
+        const int64_t u0 = sx + i * Bx - wx0, v0 = sy + j * By - wy0; /* window coords */
+        const int64_t id = (((j % nby) + nby) % nby) * nbx + (((i % nbx) + nbx) % nbx);
+        uint8_t *blk = (uint8_t *)malloc((size_t)Bx * By);
+        for (int32_t v = 0; v < By; ++v)
+            memcpy(&blk[(size_t)v * Bx], &win[(size_t)(v0 + v) * Wx + u0], (size_t)Bx);
+        /* block-local position of lattice site (0,0), if inside this block */
+        const int64_t x0 = ((sx + i * Bx) % Lx + Lx) % Lx, y0 = ((sy + j * By) % Ly + Ly) % Ly;
+        const int64_t u00 = (Lx - x0) % Lx, v00 = (Ly - y0) % Ly;
+        const int32_t su = (u00 < Bx && v00 < By) ? (int32_t)u00 : -1;
+        const int32_t sv = (u00 < Bx && v00 < By) ? (int32_t)v00 : -1;
+        int64_t h = 0;
+        if (or_block_sweep(blk, Bx, By, C, seed, s, (uint32_t)id, Tp, Tq, su, sv, &h, NULL,
+                           NULL, NULL, delayed) != 0)
+            bad = 1;
+        for (int32_t v = 0; v < By; ++v)
+            memcpy(&win[(size_t)(v0 + v) * Wx + u0], &blk[(size_t)v * Bx], (size_t)Bx);
+        dh += h;
+        free(blk);
+    }
+    if (H0) *H0 += dh;
+    *vx0 = sx + i0 * Bx - wx0;
+    *vx1 = sx + i1 * Bx - wx0;
+    *vy0 = sy + j0 * By - wy0;
+    *vy1 = sy + j1 * By - wy0;
+    return bad ? -1 : 0;
 }

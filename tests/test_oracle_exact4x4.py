@@ -97,3 +97,34 @@ def test_tiled_and_rsu_laws_differ_at_small_size():
     ens = oracle.ensemble(4, 4, 1.0, 0.0, seed0=5, R=R, tmax=1, rsu=False)
     rsu_law = E.w2_law(E.evolve(E.rsu_mcs_matrix(1.0, 0.0), [1])[1])
     assert _histogram_test(ens[:, 0, :], rsu_law) < 1e-6
+
+
+# Mean W^2 of the random-sequential chain on the 4x4 torus from the flat
+# state, at t = 1, 2, 10 MCS and in the stationary state, as found by a
+# separate enumeration of the same master equation written independently of
+# this package (its t = 1 value for p = 1 was also checked by a Monte Carlo
+# run: 0.49448 +- 0.00038).  Six digits; the p = q stationary value is the
+# closed form 92/165 of the uniform law.
+I9_RSU_MEAN_W2 = {
+    (1.0, 0.0): (0.494399, 0.545255, 0.583881, 0.583896),
+    (0.95, 0.05): (0.500674, 0.543048, 0.580712, 0.580730),
+    (0.5, 0.5): (0.529193, 0.549880, 0.557547, 92 / 165),
+}
+
+
+@pytest.mark.parametrize("pq", sorted(I9_RSU_MEAN_W2))
+def test_random_sequential_law_matches_fixed_values(pq):
+    """Fixed values pin the enumerator at p != q, where no closed form holds:
+    a wrong rate, a transposed matrix or a wrong attempt count per MCS moves
+    these means far beyond the sixth digit."""
+    want = I9_RSU_MEAN_W2[pq]
+    M = E.rsu_mcs_matrix(*pq)
+    laws = E.evolve(M, [1, 2, 10])
+    got = [E.mean_w2(laws[t]) for t in (1, 2, 10)]
+    # stationary law: the left eigenvector of eigenvalue 1
+    w, v = np.linalg.eig(M.T)
+    pi = np.real(v[:, np.argmin(np.abs(w - 1.0))])
+    pi = pi / pi.sum()
+    got.append(E.mean_w2(pi))
+    for g, x in zip(got, want):
+        assert abs(g - x) < 1e-6, (pq, got, want)
