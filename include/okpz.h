@@ -174,6 +174,14 @@ int okpz_free(okpz_sim *s);
 /* Message of the last error on this thread ("" if none). */
 const char *okpz_last_error(void);
 
+/* Measurement times of Sec. III: t_{i+1} = (t_i + 10) e^m from t_0 = 0, each
+ * rounded up to a whole MCS, repeats dropped, then t_max itself (none for
+ * t_max = 0).  These are the times at which batches and servers record
+ * widths.  *n receives the number of times; with times != NULL they are
+ * written there (cap >= *n entries, else OKPZ_EINVAL).  m in (0, 10],
+ * 0 <= t_max < 2^32.  Host only: needs no device. */
+int okpz_sampling_times(int64_t t_max, double m, int64_t *times, int64_t cap, int64_t *n);
+
 /* ------------------------------------------------------------------------
  * Batched ensembles: many independent realizations of uneven size, each with
  * its own p, q, seed and length, run to completion in one persistent launch

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "okpz.h"
+#include "host_logic.h"
 #include "okpz_internal.h"
 #include "psd.h"
 #include "width.h"
@@ -70,7 +71,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 size_t plane_bytes(int64_t Lx, int64_t Ly) { return 2 * (size_t)Ly * (size_t)(Lx / 32) * 4; }
 
-bool size_ok(int64_t L) { return L >= 32 && L <= (int64_t(1) << 20) && L % 32 == 0; }
+bool size_ok(int64_t L) { return okpz::host::side_ok(L); }
 
 bool prob_ok(double v) { return v >= 0.0 && v <= 1.0; }
 
@@ -228,44 +229,6 @@ void unpack_rows(const okpz_sim *s, int64_t n, const std::vector<uint32_t> &pl0,
         }
 }
 
-bool valid_slope_field(const uint8_t *h, int64_t Lx, int64_t Ly, std::string &why)
-{
-    for (int64_t i = 0; i < Lx * Ly; ++i)
-        if (h[i] > 3) {
-            why = "byte > 3";
-            return false;
-        }
-    for (int64_t y = 0; y < Ly; ++y) {
-        int64_t sum = 0;
-        for (int64_t x = 0; x < Lx; ++x) sum += (h[y * Lx + x] & 1) ? 1 : -1;
-        if (sum) {
-            why = "sigma_x row sum not zero";
-            return false;
-        }
-    }
-    for (int64_t x = 0; x < Lx; ++x) {
-        int64_t sum = 0;
-        for (int64_t y = 0; y < Ly; ++y) sum += (h[y * Lx + x] & 2) ? 1 : -1;
-        if (sum) {
-            why = "sigma_y column sum not zero";
-            return false;
-        }
-    }
-    for (int64_t y = 0; y < Ly; ++y)
-        for (int64_t x = 0; x < Lx; ++x) {
-            const int64_t x1 = (x + 1) % Lx, y1 = (y + 1) % Ly;
-            const int a = (h[y * Lx + x] & 1) ? 1 : -1;
-            const int b = (h[y * Lx + x1] & 2) ? 1 : -1;
-            const int c = (h[y1 * Lx + x] & 1) ? 1 : -1;
-            const int d = (h[y * Lx + x] & 2) ? 1 : -1;
-            if (a + b - c - d != 0) {
-                why = "plaquette not closed";
-                return false;
-            }
-        }
-    return true;
-}
-
 int upload_lattice(okpz_sim *s, const uint8_t *host)
 {
     const size_t W = (size_t)s->W;
@@ -283,17 +246,7 @@ int upload_lattice(okpz_sim *s, const uint8_t *host)
     return OKPZ_OK;
 }
 
-struct CkptHeader {
-    char magic[8];
-    uint32_t version;
-    uint32_t cell_borders;  // 0 in checkpoints of dead-border runs
-    int64_t Lx, Ly;
-    double p, q;
-    uint64_t seed;
-    int64_t t, H0;
-    int32_t ox;
-    int32_t copies;  // 1 for a sim updated in place; 0 or 2 otherwise
-};
+using okpz::host::CkptHeader;
 
 }  // namespace
 
@@ -556,8 +509,10 @@ int okpz_set_lattice(okpz_sim *s, const uint8_t *host, size_t bytes, int64_t H0,
     if (!s || !host) return fail(OKPZ_EINVAL, "null argument");
     if (bytes < (size_t)(s->Lx * s->Ly)) return fail(OKPZ_EINVAL, "host buffer too small");
     if (t < 0 || t >= (int64_t(1) << 32)) return fail(OKPZ_EINVAL, "t out of range");
+    if (!okpz::host::valid_h0(H0))
+        return fail(OKPZ_EINVAL, "height of site (0,0) must be even (h = x + y mod 2)");
     std::string why;
-    if (!valid_slope_field(host, s->Lx, s->Ly, why))
+    if (!okpz::host::valid_slope_field(host, s->Lx, s->Ly, why))
         return fail(OKPZ_EINVAL, "not a valid slope field: %s", why.c_str());
     int rc = upload_lattice(s, host);
     if (rc != OKPZ_OK) return rc;
@@ -605,20 +560,15 @@ int okpz_load(okpz_sim **out, const void *buf, size_t bytes)
     if (!out || !buf) return fail(OKPZ_EINVAL, "null argument");
     *out = nullptr;
     CkptHeader h;
-    if (bytes < sizeof h) return fail(OKPZ_EINVAL, "checkpoint truncated");
-    std::memcpy(&h, buf, sizeof h);
-    if (std::memcmp(h.magic, "OKPZCKP1", 8) != 0 || h.version != 1)
-        return fail(OKPZ_EINVAL, "not an okpz checkpoint");
-    if (!size_ok(h.Lx) || !size_ok(h.Ly) || h.ox < 0 || h.ox >= h.Lx || h.t < 0 ||
-        h.cell_borders > OKPZ_CELLS_DELAYED || h.copies < 0 || h.copies > 2)
-        return fail(OKPZ_EINVAL, "corrupt checkpoint header");
+    const uint32_t *planes = nullptr;
+    std::string why;
+    if (!okpz::host::parse_checkpoint(buf, bytes, &h, &planes, why))
+        return fail(OKPZ_EINVAL, "%s", why.c_str());
     const size_t pb = plane_bytes(h.Lx, h.Ly);
-    if (bytes < sizeof h + pb) return fail(OKPZ_EINVAL, "checkpoint truncated");
     okpz_sim *s = nullptr;
     int rc = make_sim(&s, h.Lx, h.Ly, h.p, h.q, h.seed, nullptr, 0, nullptr, h.copies == 1 ? 1 : 2);
     if (rc != OKPZ_OK) return rc;
-    hipError_t e = hipMemcpy(s->buf[0], static_cast<const char *>(buf) + sizeof h, pb,
-                             hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(s->buf[0], planes, pb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         release(s);
         return hip_fail(e, "hipMemcpy(checkpoint)");
@@ -673,6 +623,20 @@ int okpz_free(okpz_sim *s)
 {
     if (!s) return OKPZ_OK;
     release(s);
+    return OKPZ_OK;
+}
+
+int okpz_sampling_times(int64_t t_max, double m, int64_t *times, int64_t cap, int64_t *n)
+{
+    if (!n) return fail(OKPZ_EINVAL, "null argument");
+    if (!(m > 0.0) || m > 10.0) return fail(OKPZ_EINVAL, "sampling exponent m must be in (0, 10]");
+    if (t_max < 0 || t_max >= (int64_t(1) << 32)) return fail(OKPZ_EINVAL, "t_max out of range");
+    const std::vector<int64_t> v = okpz::host::sample_times(t_max, m);
+    *n = (int64_t)v.size();
+    if (times) {
+        if (cap < *n) return fail(OKPZ_EINVAL, "%lld times need room, %lld given", (long long)*n, (long long)cap);
+        std::copy(v.begin(), v.end(), times);
+    }
     return OKPZ_OK;
 }
 

@@ -34,6 +34,7 @@
 #include <string>
 #include <vector>
 
+#include "host_logic.h"
 #include "okpz.h"
 #include "sweep_core.h"
 #include "width.h"
@@ -398,19 +399,12 @@ int bfail(int code, const char *fmt, ...)
 
 bool side_ok(int64_t L) { return L >= 32 && L <= 8192 && L % 32 == 0; }
 
+// Measurement times of Sec. III as the 32-bit sweep counts the job tables
+// hold (t_max < 2^31 is checked at submission).
 std::vector<int32_t> sample_times(int64_t t_max, double m)
 {
-    std::vector<int32_t> out;
-    if (t_max <= 0) return out;
-    double t = 0.0;
-    while (true) {
-        t = (t + 10.0) * std::exp(m);
-        if (t > (double)t_max) break;
-        const int32_t c = (int32_t)std::ceil(t);
-        if (out.empty() || out.back() != c) out.push_back(c);
-    }
-    if (out.empty() || out.back() != t_max) out.push_back((int32_t)t_max);
-    return out;
+    const std::vector<int64_t> v = okpz::host::sample_times(t_max, m);
+    return std::vector<int32_t>(v.begin(), v.end());
 }
 
 size_t al(size_t n) { return (n + 255) / 256 * 256; }

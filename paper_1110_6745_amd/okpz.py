@@ -85,6 +85,7 @@ _sig("okpz_get_cell_borders", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int32))
 _sig("okpz_sync", ctypes.c_int, _vp)
 _sig("okpz_free", ctypes.c_int, _vp)
 _sig("okpz_last_error", ctypes.c_char_p)
+_sig("okpz_sampling_times", ctypes.c_int, _i64, ctypes.c_double, _i64p, _i64, _i64p)
 
 class OkpzJob(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int64), ("Ly", ctypes.c_int64), ("p", ctypes.c_double),
@@ -133,7 +134,8 @@ EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_width", "okpz_w2", "okpz_psd", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
             "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads",
             "okpz_set_cell_borders", "okpz_get_cell_borders", "okpz_sync",
-            "okpz_free", "okpz_last_error", "okpz_batch_create", "okpz_batch_set_mapping",
+            "okpz_free", "okpz_last_error", "okpz_sampling_times", "okpz_batch_create",
+            "okpz_batch_set_mapping",
             "okpz_batch_get_mapping", "okpz_batch_set_cell_borders",
             "okpz_batch_get_cell_borders", "okpz_batch_autotune", "okpz_batch_run",
             "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
@@ -192,10 +194,12 @@ def okpz_init_in_place(Lx: int, Ly: int, p: float, q: float, seed: int, dev_ptr:
     return Sim(h, Lx, Ly)
 
 
-def okpz_load(buf: bytes) -> "Sim":
+def okpz_load(buf) -> "Sim":
+    """A checkpoint from any bytes-like object (bytes, bytearray, uint8 array),
+    passed without a copy."""
     h = _vp()
-    b = ctypes.create_string_buffer(buf, len(buf))
-    _check(_lib.okpz_load(ctypes.byref(h), b, len(buf)))
+    view = np.frombuffer(buf, dtype=np.uint8)
+    _check(_lib.okpz_load(ctypes.byref(h), _vp(view.ctypes.data), view.nbytes))
     sim = Sim(h, 0, 0)
     sim.Ly, sim.Lx = sim._shape_from_lattice_size(buf)
     return sim
@@ -430,20 +434,12 @@ class Batch:
 
 
 def sampling_times(t_max: int, m: float) -> list:
-    """ceil of t_{i+1} = (t_i + 10) e^m, t_0 = 0, duplicates dropped, plus t_max."""
-    import math
-
-    out, t = [], 0.0
-    while True:
-        t = (t + 10.0) * math.exp(m)
-        if t > t_max:
-            break
-        c = int(math.ceil(t))
-        if not out or out[-1] != c:
-            out.append(c)
-    if t_max > 0 and (not out or out[-1] != t_max):
-        out.append(int(t_max))
-    return out
+    """Measurement times of Sec. III (okpz_sampling_times)."""
+    n = ctypes.c_int64()
+    _check(_lib.okpz_sampling_times(int(t_max), float(m), None, 0, ctypes.byref(n)))
+    out = (ctypes.c_int64 * max(n.value, 1))()
+    _check(_lib.okpz_sampling_times(int(t_max), float(m), out, n.value, ctypes.byref(n)))
+    return [int(v) for v in out[:n.value]]
 
 
 class Server:

@@ -112,3 +112,76 @@ def test_header_is_c99_and_host_calls_work_from_c(tmp_path):
     out = subprocess.run([exe, "host"], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "host ok"
+
+
+@pytest.mark.parametrize("m", [0.001, 0.01, 0.0663, 0.5, 3.0, 10.0])
+def test_sampling_times_equal_the_oracle(m):
+    # the library's one implementation against the oracle's own
+    from paper_1110_6745_amd import okpz
+
+    for t_max in (0, 1, 9, 11, 100, 4096, 10000, 1_310_720):
+        assert okpz.sampling_times(t_max, m) == oracle.sampling_times(t_max, m), (t_max, m)
+
+
+@pytest.mark.parametrize("t_max,m", [(100, 0.0), (100, -0.1), (100, 10.5), (-1, 0.01),
+                                     (1 << 32, 0.01), (100, float("nan"))])
+def test_sampling_times_reject_bad_arguments(t_max, m):
+    from paper_1110_6745_amd import okpz
+
+    with pytest.raises(okpz.OkpzError) as e:
+        okpz.sampling_times(t_max, m)
+    assert e.value.code == okpz.OKPZ_EINVAL
+
+
+def _flat_checkpoint(Lx=64, Ly=32, H0=0, ox=0, t=5):
+    """A checkpoint of the flat state: the 80-byte header of include/okpz.h's
+    okpz_save layout, then the sigma_x and sigma_y bit planes."""
+    import struct
+
+    import numpy as np
+
+    hdr = struct.pack("<8sIIqqddQqqii", b"OKPZCKP1", 1, 0, Lx, Ly, 1.0, 0.0, 7, t, H0, ox, 2)
+    assert len(hdr) == 80
+    W = Lx // 32
+    rows = np.array([0x55555555 if y % 2 == 0 else 0xAAAAAAAA for y in range(Ly)], np.uint32)
+    plane = np.repeat(rows, W)
+    return bytearray(hdr + plane.tobytes() + plane.tobytes())
+
+
+def _load_code(buf):
+    from paper_1110_6745_amd import okpz
+
+    try:
+        sim = okpz.okpz_load(bytes(buf))
+    except okpz.OkpzError as e:
+        return e.code
+    sim.free()  # a device was there and the checkpoint loaded
+    return okpz.OKPZ_OK
+
+
+def test_load_rejects_corrupt_checkpoints_before_any_device_call():
+    from paper_1110_6745_amd import okpz
+
+    good = _flat_checkpoint()
+    # the valid checkpoint passes validation (on a host without a device the
+    # allocation that follows fails instead)
+    assert _load_code(good) != okpz.OKPZ_EINVAL
+    bad = bytearray(good)
+    bad[0:8] = b"OKPZCKP2"
+    assert _load_code(bad) == okpz.OKPZ_EINVAL
+    assert _load_code(good[:-1]) == okpz.OKPZ_EINVAL           # truncated planes
+    assert _load_code(good[:40]) == okpz.OKPZ_EINVAL           # truncated header
+    assert _load_code(_flat_checkpoint(H0=3)) == okpz.OKPZ_EINVAL  # odd h(0,0)
+    assert _load_code(_flat_checkpoint(ox=64)) == okpz.OKPZ_EINVAL
+    assert _load_code(_flat_checkpoint(Lx=48)) == okpz.OKPZ_EINVAL
+    assert _load_code(_flat_checkpoint(t=-1)) == okpz.OKPZ_EINVAL
+    # one flipped slope bit opens two plaquettes and breaks a row sum
+    bad = bytearray(good)
+    bad[80 + 4 * 5] ^= 0x10
+    assert _load_code(bad) == okpz.OKPZ_EINVAL
+    # one flipped sigma_y bit
+    bad = bytearray(good)
+    bad[80 + 64 * 32 // 8 + 9] ^= 0x01
+    assert _load_code(bad) == okpz.OKPZ_EINVAL
+    # a rotated valid field (stored columns shifted) is still valid
+    assert _load_code(_flat_checkpoint(ox=17)) != okpz.OKPZ_EINVAL
