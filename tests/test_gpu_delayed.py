@@ -139,11 +139,14 @@ def test_full_size_one_sweep_on_sampled_blocks(okpz):
     sim.free()
 
 
-def test_growth_width_against_random_sequential(okpz):
-    """Sec. II expects the decomposition to change prefactors at most, not
-    exponents: the excess width W^2 - 1/4 of both border contracts (GPU) and
-    of the random-sequential reference (oracle) during growth, averaged over
-    seeds, agree within their statistical errors.  Prints the table."""
+def test_growth_width_prefactor_report(okpz):
+    """Excess width W^2 - 1/4 during growth (L = 256, p = 1, 12 seeds) of both
+    border contracts (GPU) and of the random-sequential reference (oracle).
+    Sec. II expects the decomposition to change prefactors, not exponents, so
+    the tiled widths may differ from the reference's by a constant factor
+    (exponents are compared in tests/test_gpu_beta.py); printed as a report.
+    The two tiled contracts differ only in how the cell borders wait, and
+    their widths agree within 4 combined standard errors at every time."""
     L, R, p, q = 256, 12, 1.0, 0.0
     times = [10, 30, 100, 200]
     N = L * L
@@ -152,8 +155,8 @@ def test_growth_width_against_random_sequential(okpz):
         S1, S2 = S1S2[..., 0].astype(object), S1S2[..., 1].astype(object)
         return np.array((N * S2 - S1 * S1) / (N * N), dtype=float) - 0.25
 
-    rsu = oracle.ensemble(L, L, p, q, seed0=500, R=R, tmax=max(times), rsu=True)
-    rows = {"rsu": np.array([excess(rsu[:, t - 1, :]) for t in times]).T}
+    rsu = oracle.ensemble_at(L, L, p, q, seed0=500, R=R, times=times, rsu=True)
+    rows = {"rsu": excess(rsu)}
     for kind, name in ((okpz.OKPZ_CELLS_DEAD, "dead"), (okpz.OKPZ_CELLS_DELAYED, "delayed")):
         w = np.zeros((R, len(times)))
         for r in range(R):
@@ -166,8 +169,13 @@ def test_growth_width_against_random_sequential(okpz):
     print(f"\nexcess W^2, L={L}, {R} seeds: t " + " ".join(f"{t:>8d}" for t in times))
     for name, w in rows.items():
         print(f"{name:>8s}: " + " ".join(f"{m:8.4f}" for m in w.mean(axis=0)))
+
+    def z(a, b):
+        d = rows[a].mean(axis=0) - rows[b].mean(axis=0)
+        return d / np.sqrt(rows[a].var(axis=0, ddof=1) / R + rows[b].var(axis=0, ddof=1) / R)
+
     for name in ("dead", "delayed"):
-        d = rows[name].mean(axis=0) - rows["rsu"].mean(axis=0)
-        err = np.sqrt(rows[name].var(axis=0, ddof=1) / R + rows["rsu"].var(axis=0, ddof=1) / R)
-        print(f"{name:>8s} - rsu in standard errors: " + " ".join(f"{v:6.2f}" for v in d / err))
-        assert np.all(np.abs(d) < 5 * err + 0.02 * rows["rsu"].mean(axis=0)), name
+        print(f"{name:>8s} / rsu: " + " ".join(
+            f"{v:8.4f}" for v in rows[name].mean(axis=0) / rows["rsu"].mean(axis=0))
+            + "   in standard errors: " + " ".join(f"{v:+.2f}" for v in z(name, "rsu")))
+    assert np.all(np.abs(z("dead", "delayed")) < 4.0)

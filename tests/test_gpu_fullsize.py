@@ -149,3 +149,77 @@ def test_longest_sides(okpz, Lx, Ly):
     assert np.array_equal(sim.get_lattice(), lat) and sim.h0() == H1
     check(sim.psd(), lat, H1, f"{Lx}x{Ly}")
     sim.free()
+
+
+@pytest.mark.parametrize("delayed,n_mcs,W", [(False, 20, 11264), (True, 6, 5120)])
+def test_grown_state_at_full_size_on_oracle_windows(okpz, delayed, n_mcs, W):
+    """The 2^17 x 2^17 growth run (p = 1, q = 0, seed 1) after n_mcs sweeps,
+    bit for bit on two windows the oracle computes from the flat state alone:
+    blocks of a sweep are independent (Sec. II), so a window of the flat
+    state swept by the oracle is exact on the blocks that stay inside it.  One
+    window holds site (0,0), which checks H0 of the grown surface."""
+    L = L17
+    seed, p, q = 1, 1.0, 0.0
+    sim = okpz.okpz_init(L, L, p, q, seed)
+    if delayed:
+        sim.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
+    sim.sweep(n_mcs)
+    sim.sync()
+    print(f"gpu {n_mcs} sweeps done", flush=True)
+    for name, wx0, wy0 in (("site00", -W // 2, -W // 2), ("far", 70001, 40003)):
+        win = oracle.Window(oracle.flat_window(wx0, wy0, W, W), wx0, wy0, L, L)
+        for s in range(n_mcs):
+            win.sweep(p, q, seed, s, delayed=delayed)
+        vx0, vy0, vx1, vy1 = win.valid
+        assert vx1 - vx0 >= 512 and vy1 - vy0 >= 512, win.valid
+        xs = (wx0 + np.arange(vx0, vx1)) % L
+        for y in range(vy0, vy1, 1024):
+            n = min(1024, vy1 - y)
+            got = sim.get_rows(wy0 + y, n)
+            assert np.array_equal(got[:, xs], win.lat[y:y + n, vx0:vx1]), f"{name} rows {y}.."
+        if name == "site00":
+            assert vx0 <= W // 2 < vx1 and vy0 <= W // 2 < vy1
+            assert sim.h0() == win.H0 and win.H0 > 0
+        print(f"window {name} ok: {vx1 - vx0} x {vy1 - vy0} sites", flush=True)
+    sim.free()
+
+
+def _oracle_band_sums(rows_of, Ly, H0, band=1024):
+    """S1, S2 of a surface streamed through oracle.width_rows band by band."""
+    S1 = S2 = 0
+    h = H0
+    for y0 in range(0, Ly, band):
+        a, b, h = oracle.width_rows(rows_of(y0, min(band, Ly - y0)), h)
+        S1, S2 = S1 + a, S2 + b
+    assert h == H0
+    return S1, S2
+
+
+@pytest.mark.parametrize("kind,H0", [("separable", 22000), ("diagonal", -20000),
+                                     ("separable", 24000)])
+def test_width_of_synthetic_full_size_surfaces(okpz, kind, H0):
+    """okpz_width on 2^17 x 2^17 surfaces built from closed +-1 walks and
+    loaded as checkpoints, with |H0| near the point where S2 leaves int64
+    (N = 2^34 sites, S2 ~ N H0^2): exact sums against the oracle's band by band
+    width, and OKPZ_EOVERFLOW exactly when the oracle's S2 does not fit."""
+    L = L17
+    a = inputs.balanced_bits(L, 3)
+    b = inputs.balanced_bits(L, 4)
+    ck = inputs.checkpoint_of(kind, a, b, H0)
+    sim = okpz.okpz_load(ck)
+    del ck
+    if kind == "separable":
+        rows_of = lambda y0, n: inputs.separable_rows(a, b, y0, n)  # noqa: E731
+    else:
+        rows_of = lambda y0, n: inputs.diagonal_rows(a, y0, n)  # noqa: E731
+    S1, S2 = _oracle_band_sums(rows_of, L, H0)
+    print(f"{kind} H0={H0}: oracle S1={S1} S2={S2}", flush=True)
+    fits = -(2**63) <= S1 < 2**63 and S2 < 2**63
+    if fits:
+        assert sim.width() == (S1, S2)
+        assert S2 > 2**62  # the sums really are near the int64 limit
+    else:
+        with pytest.raises(okpz.OkpzError) as e:
+            sim.width()
+        assert e.value.code == okpz.OKPZ_EOVERFLOW
+    sim.free()

@@ -140,6 +140,10 @@ def test_errors(okpz):
     bad[3, 5] ^= 1  # breaks a row sum
     with pytest.raises(okpz.OkpzError):
         sim.set_lattice(bad, 0, 0)
+    # h = x + y (mod 2): the height of site (0,0) is even
+    with pytest.raises(okpz.OkpzError) as e:
+        sim.set_lattice(oracle.flat(64, 64), 7, 0)
+    assert e.value.code == okpz.OKPZ_EINVAL
     sim.set_lattice(oracle.flat(64, 64), 2**40, 0)
     with pytest.raises(okpz.OkpzError) as e:
         sim.width()

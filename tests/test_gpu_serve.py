@@ -1,8 +1,12 @@
 """Serving with continuous batching: jobs arriving while others run are
 admitted at quantum boundaries as slots and bytes free up; every job's
-result is bit for bit the one it gives alone."""
+samples, final lattice and H0 are bit for bit the oracle's (the seeded tiled
+dynamics of Sec. II with the widths of Eq. (Wdef) at the measurement times
+of Sec. III) and the ones the job gives alone."""
 import numpy as np
 import pytest
+
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +27,32 @@ def alone(okpz, job, m):
     return ref, lat, h0
 
 
+def oracle_job(job, m, delayed=False):
+    """The oracle's run of a job from the flat state: (t, S1, S2) at the
+    measurement times, the final lattice and H0."""
+    Lx, Ly, p, q, seed, t_max = job
+    lat = oracle.flat(Lx, Ly)
+    H0, t, ref = 0, 0, []
+    for ts in oracle.sampling_times(t_max, m):
+        H0 = oracle.run(lat, p, q, seed, t, ts - t, H0, delayed=delayed)
+        t = ts
+        ref.append((ts,) + oracle.width_sums(lat, H0))
+    return ref, lat, H0
+
+
+def check_served(sv, i, job, m, delayed=False, lattice=True):
+    """Served job i against the oracle and against the job run alone."""
+    want, lat, h0 = oracle_job(job, m, delayed)
+    t, s1, s2 = sv.samples(i)
+    got = list(zip(t.tolist(), s1.tolist(), s2.tolist()))
+    assert got == want, f"job {job}: samples differ from the oracle"
+    if lattice:
+        g, gh0 = sv.result(i, lattice=True)
+        assert np.array_equal(g, lat) and gh0 == h0, f"job {job}: lattice differs from the oracle"
+    else:
+        assert sv.result(i)[1] == h0, f"job {job}: H0 differs from the oracle"
+
+
 def test_mix_equals_alone_with_staggered_arrivals(okpz):
     m = 0.2
     jobs = [(64, 64, 1.0, 0.0, 1, 40), (256, 256, 0.95, 0.05, 2, 25), (32, 32, 0.7, 0.3, 3, 60),
@@ -41,6 +71,7 @@ def test_mix_equals_alone_with_staggered_arrivals(okpz):
         assert np.array_equal(got, lat) and gh0 == h0, f"job {job}"
         info = sv.job(i)
         assert info["state"] == 2 and info["admit"] >= info["arrival"] and info["finish"] >= info["admit"]
+        check_served(sv, i, job, m)
     sv.free()
 
 
@@ -61,6 +92,8 @@ def test_large_jobs_on_plain_sweeps_equal_alone(okpz):
         assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref, f"job {job}"
         got, gh0 = sv.result(i, lattice=True)
         assert np.array_equal(got, lat) and gh0 == h0, f"job {job}"
+        check_served(sv, i, job, m)
+        print(f"job {job} equals the oracle", flush=True)
     sv.free()
 
 
@@ -77,6 +110,8 @@ def test_admission_respects_slots_and_bytes(okpz):
             break
     assert peak <= 2
     assert all(sv.job(i)["state"] == 2 for i in ids)
+    for k, i in enumerate(ids):
+        check_served(sv, i, (512, 512, 1.0, 0.0, 10 + k, 8), 1.0, lattice=False)
     # admissions happen in arrival (submission) order
     admits = [sv.job(i)["admit"] for i in ids]
     assert admits == sorted(admits)
@@ -102,6 +137,8 @@ def test_poisson_stream_small(okpz):
         t, s1, s2 = sv.samples(i)
         assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref
         assert sv.result(i)[1] == h0
+    for i in ids:
+        check_served(sv, i, sv.jobs[i], 0.5, lattice=False)
     lat = [sv.job(i)["finish"] - sv.job(i)["arrival"] for i in ids]
     assert min(lat) >= 0
     sv.free()
@@ -134,4 +171,5 @@ def test_delayed_borders_equal_alone(okpz):
         got, gh0 = sv.result(i, lattice=True)
         assert np.array_equal(got, sim.get_lattice()) and gh0 == sim.h0(), f"job {job}"
         sim.free()
+        check_served(sv, i, job, m, delayed=True)
     sv.free()
