@@ -44,51 +44,75 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def sampling_times(tmax, m=0.01):
-    """ceil of t_{i+1} = (t_i + 10) e^m, t_0 = 0 (Sec. III), up to tmax."""
-    out, t = [], 0.0
-    while True:
-        t = (t + 10.0) * math.exp(m)
-        if t > tmax:
-            return sorted(set(out))
-        out.append(int(math.ceil(t)))
-
-
-def cpu_baseline(budget_s=12.0):
-    """The oracle, untuned, on the host cores: MCS of a 4096^2 flat lattice,
-    p = 1, q = 0, seed 1 -- 256 blocks of the same 256 x 256 geometry and
-    schedule as the 2^17 workload, so the per-site work is identical."""
+def single_core_rate(L, budget_s):
+    """Oracle site updates/s of a flat L x L lattice (p = 1, q = 0, seed 1)
+    on one host core, the paper's non-parallel reference point (Sec. II)."""
     import oracle
 
-    L = 4096
-    lat = oracle.flat(L, L)
     threads = oracle.num_threads()
-    H0, s, t0 = 0, 0, time.perf_counter()
-    while True:
-        H0 = oracle.sweep(lat, 1.0, 0.0, 1, s, H0)
-        s += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or s >= 400:
-            break
-    # one core, the paper's non-parallel reference point (Sec. III)
     oracle.set_num_threads(1)
     try:
-        lat1 = oracle.flat(L, L)
-        H1, s1, t1 = 0, 0, time.perf_counter()
+        lat = oracle.flat(L, L)
+        H, s, t0 = 0, 0, time.perf_counter()
         while True:
-            H1 = oracle.sweep(lat1, 1.0, 0.0, 1, s1, H1)
-            s1 += 1
-            el1 = time.perf_counter() - t1
-            if el1 >= budget_s / 3 or s1 >= 100:
+            H = oracle.sweep(lat, 1.0, 0.0, 1, s, H)
+            s += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or s >= 400:
                 break
     finally:
         oracle.set_num_threads(threads)
-    return {"value": L * L * s / el, "unit": "site updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{s} MCS of a 4096x4096 flat lattice (p=1, q=0, seed 1; 256 blocks of the "
-                      f"2^17 workload's 256x256 geometry), {el:.1f} s, OpenMP over blocks",
-            "single_core": {"value": L * L * s1 / el1, "cores": 1,
-                            "sample": f"{s1} MCS of the same lattice, {el1:.1f} s"}}
+    return {"L": L, "mcs": s, "seconds": el, "value": L * L * s / el}
+
+
+def cpu_baseline(okpz, sim, seed, p, q, budget_s=12.0, max_block_rows=192, chunk=16):
+    """The oracle, untuned, on the host cores, on a bounded sample of the
+    benchmark's own workload: one sweep (the next MCS of the 2^17 run) of a
+    band of whole block rows, taken from the GPU's lattice before that sweep
+    and advanced with the oracle's window sweep (OpenMP over the band's
+    blocks).  The oracle's result is compared bit for bit with the GPU's
+    lattice after the sweep.  Then one core on flat 4096^2 and 8192^2
+    lattices (the paper's CPU reference is one core; Sec. II sees a jump
+    between log2 L = 12 and 13 when the lattice leaves the CPU's cache)."""
+    import numpy as np
+
+    import oracle
+
+    L = sim.Lx
+    Bx, By, _ = oracle.geometry(L, L)
+    s = sim.time()
+    sx, sy = oracle.block_shift(seed, s, Bx, By)
+    nb = min(max_block_rows, L // By)
+    chunk = min(chunk, nb)
+    y0 = sy  # block row 0 of sweep s starts at row sy
+    pre = [sim.get_rows(y0 + k * By, chunk * By) for k in range(0, nb, chunk)]
+    sim.sweep(1)
+    threads = oracle.num_threads()
+    done, el, checked = 0, 0.0, 0
+    for k, rows in enumerate(pre):
+        w = oracle.Window(rows, 0, (y0 + k * chunk * By) % L, L, L, 0)
+        t0 = time.perf_counter()
+        w.sweep(p, q, seed, s)
+        el += time.perf_counter() - t0
+        vx0, vy0, vx1, vy1 = w.valid
+        done += (vx1 - vx0) * (vy1 - vy0)
+        post = sim.get_rows(y0 + k * chunk * By, chunk * By)
+        if not np.array_equal(post[vy0:vy1, vx0:vx1], rows[vy0:vy1, vx0:vx1]):
+            raise AssertionError(f"GPU sweep {s} differs from the oracle in block rows "
+                                 f"{k * chunk}..{(k + 1) * chunk - 1}")
+        checked += (vx1 - vx0) // Bx * ((vy1 - vy0) // By)
+        if el >= budget_s:
+            break
+    del pre
+    single = [single_core_rate(n, budget_s / 4) for n in (4096, 8192)]
+    return {"value": done / el, "unit": "site updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"sweep {s} (MCS {s + 1}) of the {L}x{L} run, {checked} blocks of "
+                      f"{Bx}x{By} ({done} site updates) in whole block rows from the GPU's "
+                      f"lattice before the sweep, oracle window sweep with OpenMP over blocks, "
+                      f"{el:.1f} s; result equal bit for bit to the GPU's",
+            "single_core": {"cores": 1, "value": single[0]["value"],
+                            "sample": "flat 4096x4096, p=1 q=0, seed 1",
+                            "by_L": single}}
 
 
 def ensemble_jobs(scale):
@@ -102,10 +126,16 @@ def ensemble_jobs(scale):
     return jobs
 
 
-def batch_leg(scale, m=0.001):
+def batch_leg(scale, m=0.001, plain_scale=None):
     """Realizations/s of the ensemble: one persistent launch (after the
     autotuner picks the mapping) vs a per-realization loop of okpz_sweep /
-    okpz_width launches, same jobs, same sampling times, same GPU."""
+    okpz_width launches, same jobs, same sampling times, same GPU.
+
+    plain_scale: time the per-realization loop on one realization per size
+    at t = plain_scale x 20 L^1.6 instead of all 512 at `scale`, and
+    extrapolate: the loop's time is one launch per MCS and per sample plus a
+    fixed cost per realization, so it grows linearly in t and in the number
+    of realizations (16 per size)."""
     from paper_1110_6745_amd import okpz
 
     jobs = ensemble_jobs(scale)
@@ -117,7 +147,7 @@ def batch_leg(scale, m=0.001):
     t0 = time.perf_counter()
     dev_ms = b.run()
     batched_s = time.perf_counter() - t0
-    log(f"ensemble: batched {batched_s:.2f} s (mapping {mapping})")
+    log(f"ensemble: batched {batched_s:.2f} s + autotune {tune_s:.2f} s (mapping {mapping})")
     # spot check: one job of each size class run alone gives the same samples
     for r in (0, 31):
         L, _, p, q, seed, t_max = jobs[r]
@@ -127,27 +157,88 @@ def batch_leg(scale, m=0.001):
         t, s1, s2 = b.samples(r)
         assert list(zip(t.tolist(), s1.tolist(), s2.tolist())) == ref, "batched job differs"
     hist_L = 1024
-    t_from = jobs[31][5] // 2
+    # steady state: W^2 of L = 1024 saturates near t_x ~ L^z, z ~ 1.6 (Sec. IV);
+    # samples from 2 L^1.6 on when the run reaches it, else the growth regime
+    t_sat = int(2 * hist_L ** 1.6)
+    t_from = t_sat if jobs[31][5] > t_sat else jobs[31][5] // 2
+    regime = "steady state (t >= 2 L^1.6)" if t_from == t_sat else "growth regime (t < 2 L^1.6)"
     counts, under, over = b.w2_histogram(hist_L, hist_L, t_from, 0.0, 20.0, 40)
     n_cum, _, kappa = b.w2_cumulants(hist_L, hist_L, t_from)
     b.free()
-    t0 = time.perf_counter()
-    for L, _, p, q, seed, t_max in jobs:
-        sim = okpz.okpz_init(L, L, p, q, seed)
-        for t in okpz.sampling_times(t_max, m):
-            sim.width(t)
-        sim.free()
-    plain_s = time.perf_counter() - t0
+    if plain_scale is None:
+        t0 = time.perf_counter()
+        for L, _, p, q, seed, t_max in jobs:
+            sim = okpz.okpz_init(L, L, p, q, seed)
+            for t in okpz.sampling_times(t_max, m):
+                sim.width(t)
+            sim.free()
+        plain_s = time.perf_counter() - t0
+        plain_how = "measured: all 512 realizations, one after another"
+    else:
+        sample = ensemble_jobs(plain_scale)[:32]
+        t0 = time.perf_counter()
+        for L, _, p, q, seed, t_max in sample:
+            sim = okpz.okpz_init(L, L, p, q, seed)
+            for t in okpz.sampling_times(t_max, m):
+                sim.width(t)
+            sim.free()
+        sample_s = time.perf_counter() - t0
+        plain_s = sample_s * 16 * scale / plain_scale
+        plain_how = (f"extrapolated: one realization per size at t = {plain_scale:g} x 20 L^1.6 "
+                     f"took {sample_s:.2f} s, x 16 per size x {scale / plain_scale:g} in t")
     return {"workload": f"512 realizations, L = 32..1024 step 32 (16 each), p=1 q=0, "
-                        f"t = {scale:g} x 20 L^1.6 MCS, W^2 at t_(i+1)=(t_i+10)e^{m:g}",
-            "site_updates": work, "batched_s": batched_s, "batched_device_ms": dev_ms,
-            "plain_s": plain_s, "realizations_per_s_batched": 512 / batched_s,
+                        f"t = {scale:g} x 20 L^1.6 MCS (scale {scale:g} of the full run), "
+                        f"W^2 at t_(i+1)=(t_i+10)e^{m:g}",
+            "scale": scale, "site_updates": work, "batched_s": batched_s,
+            "batched_device_ms": dev_ms, "autotune_s": tune_s,
+            "plain_s": plain_s, "plain": plain_how,
+            "realizations_per_s_batched": 512 / batched_s,
+            "realizations_per_s_batched_incl_autotune": 512 / (batched_s + tune_s),
             "realizations_per_s_plain": 512 / plain_s, "speedup": plain_s / batched_s,
+            "speedup_incl_autotune": plain_s / (batched_s + tune_s),
             "batched_site_updates_per_s": work / batched_s,
-            "mapping": {"threads": mapping[0], "workgroups": mapping[1], "autotune_s": tune_s},
-            "w2_histogram_L1024": {"t_from": t_from, "lo": 0.0, "hi": 20.0,
+            "mapping": {"threads": mapping[0], "workgroups": mapping[1]},
+            "w2_histogram_L1024": {"t_from": t_from, "regime": regime, "lo": 0.0, "hi": 20.0,
                                    "counts": counts.tolist(), "under": under, "over": over},
-            "w2_cumulants_L1024": {"t_from": t_from, "samples": n_cum, "kappa": kappa.tolist()}}
+            "w2_cumulants_L1024": {"t_from": t_from, "regime": regime, "samples": n_cum,
+                                   "kappa": kappa.tolist()}}
+
+
+def medium_leg(t_max=10000, seeds=8, n_times=64):
+    """The medium workload: 4096 x 4096 lattices, p = 1, q = 0 and p = 0.95,
+    q = 0.05, 8 seeds each, 10^4 MCS, exact W^2 at 64 log-spaced times (the
+    Sec. III recurrence with the m that gives 64 times up to t_max), as one
+    persistent batch."""
+    from paper_1110_6745_amd import okpz
+
+    m_lo, m_hi = 1e-3, 10.0
+    for _ in range(60):  # bisect m for n_times sampling times
+        m = math.sqrt(m_lo * m_hi)
+        if len(okpz.sampling_times(t_max, m)) > n_times:
+            m_lo = m
+        else:
+            m_hi = m
+    m = m_hi
+    times = okpz.sampling_times(t_max, m)
+    L = 4096
+    jobs = [(L, L, p, q, 1 + r, t_max) for p, q in ((1.0, 0.0), (0.95, 0.05)) for r in range(seeds)]
+    b = okpz.Batch(jobs, m)
+    t0 = time.perf_counter()
+    dev_ms = b.run()
+    el = time.perf_counter() - t0
+    w2 = {}
+    for j, (_, _, p, q, _, _) in enumerate(jobs):
+        t, s1, s2 = b.samples(j)
+        w = [(L * L * int(a2) - int(a1) * int(a1)) / (L * L) ** 2 for a1, a2 in zip(s1, s2)]
+        w2.setdefault(f"p={p:g} q={q:g}", []).append(w)
+    b.free()
+    work = len(jobs) * L * L * t_max
+    return {"workload": f"{len(jobs)} realizations of {L}x{L}: (p,q) = (1,0) and (0.95,0.05), "
+                        f"{seeds} seeds each, {t_max} MCS, W^2 at {len(times)} times "
+                        f"(t_(i+1)=(t_i+10)e^m, m={m:.4f})",
+            "seconds": el, "device_ms": dev_ms, "site_updates_per_s": work / el,
+            "realizations_per_s": len(jobs) / el, "times": times,
+            "mean_w2": {k: [sum(c) / len(c) for c in zip(*v)] for k, v in w2.items()}}
 
 
 def serve_leg(n_jobs=64, rate=50.0, seed=7):
@@ -235,6 +326,33 @@ def size_scan(okpz, sizes, budget_ms=150.0):
     return out
 
 
+def delayed_leg(okpz, L, p, q, seed, steps, warmup=2):
+    """The paper's own thread-level contract, delayed cell borders (Sec. II),
+    on a second L x L lattice: mean sweep time from HIP events on the
+    lattice's stream and its HBM roofline fraction (0.5 B per site update)."""
+    import torch
+
+    sim = okpz.okpz_init(L, L, p, q, seed)
+    sim.set_cell_borders(okpz.OKPZ_CELLS_DELAYED)
+    sim.sweep(warmup)
+    st = torch.cuda.ExternalStream(sim.stream())
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a, b in ev:
+        a.record(st)
+        sim.sweep(1)
+        b.record(st)
+    ev[-1][1].synchronize()
+    sim.free()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    gbs = 0.5 * L * L / (ms * 1e-3) / 1e9
+    return {"cell_borders": "delayed", "workload": f"{L}x{L}, flat init, p=1 q=0, seed 1, "
+                                                   f"MCS {warmup}..{warmup + steps}",
+            "sweep_kernel_ms": ms, "sweep_site_updates_per_s": L * L / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +373,15 @@ def main():
                     help="one lattice copy updated in place (fits 2^20 x 2^20 on one GPU)")
     ap.add_argument("--psd-calls", type=int, default=3,
                     help="spectrum of the final surface: timed calls (0 skips it)")
+    ap.add_argument("--delayed-steps", type=int, default=20,
+                    help="delayed-border leg: timed MCS of a second lattice (0 skips it)")
+    ap.add_argument("--plain-scale", type=float, default=None,
+                    help="ensemble leg: extrapolate the per-realization loop from one "
+                         "realization per size at this fraction of 20 L^1.6")
+    ap.add_argument("--medium", action="store_true",
+                    help="also run the 4096^2 workload (2 x 8 seeds, 10^4 MCS) as one batch")
+    ap.add_argument("--w2-out", default=None,
+                    help="write every width sample of the timed steps to this JSON file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent "
@@ -288,7 +415,7 @@ def main():
     sim.sweep(args.warmup)
     torch.cuda.synchronize()
     t_lo, t_hi = args.warmup, args.warmup + args.steps
-    samples = [t for t in sampling_times(t_hi) if t_lo < t <= t_hi]
+    samples = set(t for t in okpz.sampling_times(t_hi, 0.01) if t_lo < t <= t_hi)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     widths = []
@@ -301,6 +428,8 @@ def main():
         ev[i][1].record(stream)
         if (t_lo + i + 1) in samples:
             widths.append((t_lo + i + 1,) + sim.width())
+        if args.steps >= 1000 and (i + 1) % 500 == 0:
+            log(f"step {t_lo + i + 1} of {t_hi}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -308,9 +437,19 @@ def main():
     value = N * args.steps / elapsed
     achieved_gbs = 0.5 * N / (sweep_ms * 1e-3) / 1e9
     w2 = [(t, (N * s2 - s1 * s1) / (N * N)) for t, s1, s2 in widths]
+    if args.w2_out:
+        late = ev[-min(100, args.steps):]
+        with open(args.w2_out, "w") as f:
+            json.dump({"L": L, "p": p, "q": q, "seed": seed, "t_lo": t_lo, "t_hi": t_hi,
+                       "cell_borders": args.cell_borders, "sweep_ms_mean": sweep_ms,
+                       "sweep_ms_last_100": sum(a.elapsed_time(b) for a, b in late) / len(late),
+                       "wall_s": elapsed,
+                       "samples": [{"t": t, "sum_h": s1, "sum_h2": s2,
+                                    "w2": (N * s2 - s1 * s1) / (N * N), "mean_h": s1 / N}
+                                   for t, s1, s2 in widths]}, f)
     traffic = None
     src_key = sweep_sources_hash()
-    if (L == TRAFFIC_MEASURED["L"] and not args.in_place
+    if (L == TRAFFIC_MEASURED["L"] and not args.in_place and args.cell_borders == "dead"
             and src_key == TRAFFIC_MEASURED["sources_sha256_16"]):
         traffic = TRAFFIC_MEASURED["bytes"]
     alu = None
@@ -356,22 +495,37 @@ def main():
         out["psd"] = {"L": L, "t": t_hi, "ms_per_call": psd_ms, "calls": args.psd_calls,
                       "S_direction_avg_n1_n2": [0.5 * (sx[1] + sy[1]), 0.5 * (sx[2] + sy[2])]}
         log(f"spectrum: {psd_ms:.3f} ms per call")
+    log(f"sweep leg: {sweep_ms:.3f} ms per MCS, {value:.4g} site updates/s")
+    if not args.no_cpu_baseline and args.cell_borders == "dead":
+        out["cpu_baseline"] = cpu_baseline(okpz, sim, seed, p, q)
+        log("cpu baseline done")
     sim.free()
     del buf
     torch.cuda.synchronize()
-    log(f"sweep leg: {sweep_ms:.3f} ms per MCS, {value:.4g} site updates/s")
+    if args.delayed_steps > 0 and args.cell_borders == "dead" and not args.in_place:
+        out["delayed_cells"] = delayed_leg(okpz, L, p, q, seed, args.delayed_steps)
+        log(f"delayed-border leg: {out['delayed_cells']['sweep_kernel_ms']:.3f} ms per MCS")
     if args.size_scan:
         out["size_scan"] = size_scan(okpz, [1 << k for k in range(8, 17)])
         log("size scan done")
     if args.batch_scale > 0:
-        out["batched_vs_plain"] = batch_leg(args.batch_scale)
+        out["batched_vs_plain"] = batch_leg(args.batch_scale, plain_scale=args.plain_scale)
         log(f"ensemble leg: speedup {out['batched_vs_plain']['speedup']:.3g}")
+    if args.medium:
+        out["medium"] = medium_leg()
+        log(f"medium leg: {out['medium']['seconds']:.2f} s")
     if args.serve_jobs > 0:
         out["serving"] = serve_leg(args.serve_jobs, 50.0)
         log("serving leg done")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
-        log("cpu baseline done")
+    if "cpu_baseline" in out:
+        one = out["cpu_baseline"]["single_core"]["value"]
+        out["paper_context"] = {
+            "speedup_vs_one_cpu_core": 240,
+            "hardware": "NVIDIA Tesla C2070 (Fermi) against one core of an Intel Core i5 750 "
+                        "at 3 GHz running non-parallel code; time per MCS, bare simulation "
+                        "time without host-device transfers (abstract, Sec. II, Sec. V)",
+            "this_run_vs_one_host_core": out["sweep_site_updates_per_s"] / one,
+            "note": "context only: different hardware, RNG and CPU code"}
     print(json.dumps(out), flush=True)
 
 

@@ -16,25 +16,30 @@ def hip_flags():
 
 
 def build(verbose=False):
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *hip_flags(), "-c", os.path.join(HERE, "csrc", src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc, *hip_flags(), "-c", os.path.join(HERE, "csrc", src), "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(objdir, src.replace(".cpp", ".o"))
-        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-c",
-               os.path.join(HERE, "csrc", src), "-o", obj]
+        cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-c",
+                     os.path.join(HERE, "csrc", src), "-o", obj])
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    jobs = max(1, min(len(cmds), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
     subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
                    check=True)
