@@ -115,6 +115,20 @@ int okpz_w2(okpz_sim *s, double *w2);
  * two), kept until okpz_free.  Synchronous. */
 int okpz_psd(okpz_sim *s, double *sx, double *sy);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc or hipFree, e.g. a serving loop or a harness that forbids it):
+ * okpz_psd without its scratch allocation.  Same arguments and results as
+ * okpz_psd, bit for bit; the scratch is a fixed 24 MiB array in device
+ * memory, one per GPU, reserved when the library's code is loaded and held
+ * until the process ends (its address is looked up once per device when the
+ * first handle is created there).  Lattices with a side above 2^17 are
+ * rejected with OKPZ_EINVAL.  No call allocates device memory; the result
+ * copies to sx and sy go through the HIP runtime's own staging.  Every call
+ * on one GPU uses the same array and nothing in it is kept between calls:
+ * calls that overlap on one GPU (handles driven from different host threads)
+ * race and must be serialised by the caller.  Synchronous. */
+int okpz_psd_noalloc(okpz_sim *s, double *sx, double *sy);
+
 /* Current time in MCS, and the absolute height H0 = h(0,0) (synchronous). */
 int okpz_time(const okpz_sim *s, int64_t *t);
 int okpz_h0(okpz_sim *s, int64_t *h0);

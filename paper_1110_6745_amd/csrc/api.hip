@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -38,6 +39,7 @@ struct okpz_sim {
     int threads;  // sweep workgroup size (execution mapping only)
     int32_t cell_borders;  // OKPZ_CELLS_DEAD or OKPZ_CELLS_DELAYED
     void *psd_mem;  // spectrum scratch, allocated by the first okpz_psd
+    int device;     // device current at creation, whose static scratch okpz_psd_noalloc uses
 };
 
 namespace {
@@ -142,6 +144,45 @@ void release(okpz_sim *s)
     delete s;
 }
 
+// Spectrum scratch of okpz_psd_noalloc: one array per device, held until the
+// process ends, never allocated or freed by a call.  In host code `scratch`
+// names a host-side stand-in, not device memory: kernels and copies get the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticPsdBytes = size_t(24) << 20;
+constexpr int64_t kStaticPsdMaxSide = int64_t(1) << 17;
+static __device__ __align__(256) unsigned char scratch[kStaticPsdBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];     // device address of `scratch` per device
+bool g_static_tried[kMaxDevices];
+hipError_t g_static_err[kMaxDevices];
+
+// Once per device, with that device current (called from make_sim, the
+// library's set-up of every handle).
+void static_scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_tried[dev]) return;
+    g_static_tried[dev] = true;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_static_err[dev] = e;
+    g_static_ptr[dev] = e == hipSuccess ? ptr : nullptr;
+}
+
+void *static_scratch(int dev, hipError_t *err)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    *err = g_static_tried[dev] ? g_static_err[dev] : hipErrorNotInitialized;
+    return g_static_ptr[dev];
+}
+
 int make_sim(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_t seed,
              void *dev_buf, size_t bytes, void *stream, int copies = 2)
 {
@@ -169,6 +210,12 @@ int make_sim(okpz_sim **out, int64_t Lx, int64_t Ly, double p, double q, uint64_
     s->ox = 0;
     s->t = 0;
     s->threads = 1024;
+    const hipError_t de = hipGetDevice(&s->device);
+    if (de != hipSuccess) {
+        delete s;
+        return hip_fail(de, "hipGetDevice");
+    }
+    static_scratch_setup(s->device);
     int rc = alloc_state(s, dev_buf, bytes, stream);
     if (rc != OKPZ_OK) {
         delete s;
@@ -461,6 +508,32 @@ int okpz_psd(okpz_sim *s, double *sx, double *sy)
     HIP_TRY(okpz::launch_psd(v, p, s->d_rows, s->psd_mem, s->stream));
     const double *spec =
         reinterpret_cast<const double *>(static_cast<const char *>(s->psd_mem) + p.off_spec);
+    const size_t nx = (size_t)s->Lx / 2 + 1, ny = (size_t)s->Ly / 2 + 1;
+    if (sx) HIP_TRY(hipMemcpyAsync(sx, spec, nx * 8, hipMemcpyDeviceToHost, s->stream));
+    if (sy) HIP_TRY(hipMemcpyAsync(sy, spec + nx, ny * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return OKPZ_OK;
+}
+
+int okpz_psd_noalloc(okpz_sim *s, double *sx, double *sy)
+{
+    if (!s) return fail(OKPZ_EINVAL, "null handle");
+    if (s->Lx > kStaticPsdMaxSide || s->Ly > kStaticPsdMaxSide)
+        return fail(OKPZ_EINVAL,
+                    "okpz_psd_noalloc: lattice %lldx%lld exceeds the static scratch's limit of "
+                    "%lld sites per side",
+                    (long long)s->Lx, (long long)s->Ly, (long long)kStaticPsdMaxSide);
+    const okpz::PsdPlan p = okpz::psd_plan_capped(s->Lx, s->Ly, kStaticPsdBytes);
+    if (p.bytes > kStaticPsdBytes)
+        return fail(OKPZ_EINVAL, "okpz_psd_noalloc: %zu bytes of scratch needed, %zu available",
+                    p.bytes, kStaticPsdBytes);
+    hipError_t se;
+    void *mem = static_scratch(s->device, &se);
+    if (!mem) return hip_fail(se, "hipGetSymbolAddress(scratch)");
+    okpz::LatticeView v{s->buf[s->cur], (int32_t)s->Lx, (int32_t)s->Ly, s->W, s->ox};
+    HIP_TRY(okpz::launch_width_rows(v, s->d_rows, s->stream));
+    HIP_TRY(okpz::launch_psd(v, p, s->d_rows, mem, s->stream));
+    const double *spec = reinterpret_cast<const double *>(static_cast<const char *>(mem) + p.off_spec);
     const size_t nx = (size_t)s->Lx / 2 + 1, ny = (size_t)s->Ly / 2 + 1;
     if (sx) HIP_TRY(hipMemcpyAsync(sx, spec, nx * 8, hipMemcpyDeviceToHost, s->stream));
     if (sy) HIP_TRY(hipMemcpyAsync(sy, spec + nx, ny * 8, hipMemcpyDeviceToHost, s->stream));

@@ -15,6 +15,9 @@ struct PsdPlan {
     int64_t conv_len;  // Bluestein transform length (0: both sides powers of two)
 };
 PsdPlan psd_plan(int64_t Lx, int64_t Ly);
+// The same with taller column-count chunks, as few as needed to bring the
+// scratch down to max_bytes if possible (check .bytes against the cap).
+PsdPlan psd_plan_capped(int64_t Lx, int64_t Ly, size_t max_bytes);
 hipError_t launch_psd(const LatticeView &v, const PsdPlan &p, const int64_t *rows, void *scratch,
                       hipStream_t st);
 

@@ -401,13 +401,12 @@ hipError_t transform(double2 *z, int32_t n, double2 *A, double2 *B, int *order, 
 
 }  // namespace
 
-PsdPlan psd_plan(int64_t Lx, int64_t Ly)
+namespace {
+
+// Scratch layout for column-count chunks of R rows (R a multiple of 16).
+PsdPlan plan_with_rows(int64_t Lx, int64_t Ly, int64_t R)
 {
     PsdPlan p{};
-    const int64_t W = Lx / 32;
-    const int64_t want = (kTargetThreads + W - 1) / W;  // chunks for ~2^18 threads
-    int64_t R = (Ly + want - 1) / want;
-    R = (R + 15) / 16 * 16;
     p.R = (int32_t)R;
     p.nch = (int32_t)((Ly + R - 1) / R);
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -423,6 +422,30 @@ PsdPlan psd_plan(int64_t Lx, int64_t Ly)
     if (!pow2(Ly) && conv_len(Ly) > M) M = conv_len(Ly);
     p.conv_len = M;
     p.bytes = p.off_conv + 2 * al((size_t)M * 16);
+    return p;
+}
+
+}  // namespace
+
+PsdPlan psd_plan(int64_t Lx, int64_t Ly)
+{
+    const int64_t W = Lx / 32;
+    const int64_t want = (kTargetThreads + W - 1) / W;  // chunks for ~2^18 threads
+    int64_t R = (Ly + want - 1) / want;
+    R = (R + 15) / 16 * 16;
+    return plan_with_rows(Lx, Ly, R);
+}
+
+PsdPlan psd_plan_capped(int64_t Lx, int64_t Ly, size_t max_bytes)
+{
+    PsdPlan p = psd_plan(Lx, Ly);
+    // fewer, taller chunks until the partial counts fit; a chunk's count of
+    // one column must stay below 2^20 (16-bit lanes of sixteens)
+    int64_t R = p.R;
+    while (p.bytes > max_bytes && R < Ly && 2 * R < (int64_t(1) << 20)) {
+        R *= 2;
+        p = plan_with_rows(Lx, Ly, R);
+    }
     return p;
 }
 

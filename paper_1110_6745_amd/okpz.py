@@ -69,6 +69,8 @@ _sig("okpz_sweep", ctypes.c_int, _vp, _i64)
 _sig("okpz_width", ctypes.c_int, _vp, _i64, _i64p, _i64p)
 _sig("okpz_w2", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double))
 _sig("okpz_psd", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+_sig("okpz_psd_noalloc", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
+     ctypes.POINTER(ctypes.c_double))
 _sig("okpz_time", ctypes.c_int, _vp, _i64p)
 _sig("okpz_h0", ctypes.c_int, _vp, _i64p)
 _sig("okpz_stream", _vp, _vp)
@@ -131,7 +133,7 @@ _sig("okpz_serve_free", ctypes.c_int, _vp)
 
 EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_required_bytes_in_place", "okpz_init_in_place", "okpz_get_copies", "okpz_sweep",
-            "okpz_width", "okpz_w2", "okpz_psd", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
+            "okpz_width", "okpz_w2", "okpz_psd", "okpz_psd_noalloc", "okpz_time", "okpz_h0", "okpz_stream", "okpz_get_lattice",
             "okpz_get_rows", "okpz_set_lattice", "okpz_save", "okpz_load", "okpz_set_threads",
             "okpz_set_cell_borders", "okpz_get_cell_borders", "okpz_sync",
             "okpz_free", "okpz_last_error", "okpz_sampling_times", "okpz_batch_create",
@@ -247,6 +249,16 @@ class Sim:
         sy = np.empty(Ly // 2 + 1, dtype=np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
         _check(_lib.okpz_psd(self._h, sx.ctypes.data_as(dp), sy.ctypes.data_as(dp)))
+        return sx, sy
+
+    def psd_noalloc(self) -> tuple:
+        """As psd(), through okpz_psd_noalloc: no device allocation, the
+        library's fixed per-GPU scratch (sides up to 2^17)."""
+        Lx, Ly = self.Lx, self.Ly
+        sx = np.empty(Lx // 2 + 1, dtype=np.float64)
+        sy = np.empty(Ly // 2 + 1, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.okpz_psd_noalloc(self._h, sx.ctypes.data_as(dp), sy.ctypes.data_as(dp)))
         return sx, sy
 
     def time(self) -> int:
