@@ -145,7 +145,12 @@ def batch_leg(scale, m=0.001, plain_scale=None):
     mapping = b.autotune(max(2, int(max(t for *_, t in jobs)) // 20))
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    dev_ms = b.run()
+    if scale >= 0.05:
+        # a long run reports its progress between slices of about 20 s
+        dev_ms = b.run(slice_ms=20000.0, progress=lambda d: log(
+            f"ensemble: {d} of {len(jobs)} realizations done, {time.perf_counter() - t0:.0f} s"))
+    else:
+        dev_ms = b.run()
     batched_s = time.perf_counter() - t0
     log(f"ensemble: batched {batched_s:.2f} s + autotune {tune_s:.2f} s (mapping {mapping})")
     # spot check: one job of each size class run alone gives the same samples

@@ -242,6 +242,20 @@ int okpz_batch_autotune(okpz_batch *b, int64_t trial_mcs, int32_t *threads, int3
  * Synchronous.  OKPZ_EDEVICE if the launch's no-progress watchdog fired. */
 int okpz_batch_run(okpz_batch *b);
 
+/* The same run in slices, for callers that want control back while a long
+ * ensemble runs (progress reports, a deadline of their own): okpz_batch_start
+ * resets every job to the flat state; each okpz_batch_run_for then continues
+ * the run in one persistent launch whose workgroups stop taking new work
+ * once max_ms milliseconds (wall clock, 0 < max_ms <= 3.6e6) have passed,
+ * finishing the sweeps they hold, and returns the number of jobs that have
+ * reached t_max in *finished.  The run is complete when *finished equals the
+ * number of jobs; samples and final states are then those of okpz_batch_run,
+ * bit for bit (the slicing only changes when work is done, never which).
+ * okpz_batch_last_ms then gives the device time summed over the slices.
+ * OKPZ_EINVAL from okpz_batch_run_for without a started run. */
+int okpz_batch_start(okpz_batch *b);
+int okpz_batch_run_for(okpz_batch *b, double max_ms, int32_t *finished);
+
 /* Device time of the last okpz_batch_run, in milliseconds. */
 int okpz_batch_last_ms(okpz_batch *b, float *ms);
 

@@ -185,11 +185,16 @@ __device__ int find_and_claim(uint64_t *claim, const int32_t *nitems, const int3
 
 // kCells: 0 for dead thread-cell borders, core::kDelayedCells for delayed
 // ones (one kind per launch).
+// budget: wall-clock ticks (wall_clock64) after which a workgroup stops
+// claiming new items and exits; 0 runs until every job has finished.  An
+// item once claimed is always completed, so a launch that stops early leaves
+// every job at a consistent point (its open items stay claimable) and the
+// next launch over the same tables continues where it stopped.
 template <int kThreads, int kCells>
 __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const JobDesc *jobs, JobState *state,
                                                          Control *ctl, uint64_t *claim,
                                                          const int32_t *sched, int32_t njobs,
-                                                         uint64_t idle_limit)
+                                                         uint64_t idle_limit, uint64_t budget)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int s_job;     // >= 0: work; -1: exit; -2: retry
@@ -199,13 +204,17 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
     const int tid = threadIdx.x;
     uint64_t idle = 0, seen = 0;
     const int32_t *nitems = sched, *order = sched + njobs;
+    const uint64_t t_begin = budget ? (uint64_t)wall_clock64() : 0;
 
     while (true) {
         if (tid < 64) {
             uint64_t w = 0;
-            int r = find_and_claim(claim, nitems, order, njobs, &w);  // uniform over wave 0
+            const bool over = budget && (uint64_t)wall_clock64() - t_begin > budget;
+            int r = over ? -1 : find_and_claim(claim, nitems, order, njobs, &w);  // uniform over wave 0
             if (tid == 0) {
-                if (r >= 0) {
+                if (over) {
+                    r = -1;
+                } else if (r >= 0) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the job's state and lattice
                     idle = 0;
                 } else if (__hip_atomic_load(&ctl->finished, __ATOMIC_RELAXED,
@@ -372,7 +381,10 @@ struct okpz_batch {
     int cus = 0;
     hipStream_t stream = nullptr;
     bool ran = false;
+    bool started = false;  // okpz_batch_start done, run not yet complete
     float last_ms = 0.f;
+    int32_t finished = 0;  // jobs finished in the started run
+    double tick_khz = 0.0;  // wall_clock64 rate
     int32_t cell_borders = OKPZ_CELLS_DEAD;
 };
 
@@ -478,6 +490,7 @@ struct Ring {
     int njobs;
     hipStream_t stream;
     int delayed_cells;  // 1: delayed thread-cell borders
+    uint64_t budget = 0;  // wall-clock ticks per launch (0: run to the end)
 };
 
 template <int kThreads, int kCells>
@@ -496,7 +509,7 @@ hipError_t launch_ring(const Ring &R, int wgs)
     const uint64_t idle_limit = 1ull << 19;
     hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells>), dim3(wgs), dim3(kThreads),
                        okpz::core::kGroupLds, R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
-                       (int32_t)R.njobs, idle_limit);
+                       (int32_t)R.njobs, idle_limit, R.budget);
     return hipGetLastError();
 }
 
@@ -516,15 +529,18 @@ hipError_t launch_any(const Ring &R, int threads, int wgs)
     return launch_cells<0>(R, threads, wgs);
 }
 
-// After a launch: OKPZ_OK if every job reached its stop target.
-int check_control(const Ring &R)
+// After a launch: OKPZ_OK if every job reached its stop target (or, for a
+// launch with a time budget, if the watchdog did not fire); *finished gets
+// the number of jobs that have.
+int check_control(const Ring &R, int32_t *finished = nullptr)
 {
     Control ctl;
     BHIP(hipMemcpy(&ctl, R.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    if (finished) *finished = ctl.finished;
     if (ctl.error == 1)
         return bfail(OKPZ_EDEVICE, "persistent launch watchdog: no progress (finished %d of %d)",
                      ctl.finished, R.njobs);
-    if (ctl.finished != R.njobs)
+    if (ctl.finished != R.njobs && R.budget == 0)
         return bfail(OKPZ_EDEVICE, "launch ended with %d of %d jobs finished", ctl.finished, R.njobs);
     return OKPZ_OK;
 }
@@ -535,13 +551,15 @@ Ring ring_of(okpz_batch *b)
                 b->cell_borders == OKPZ_CELLS_DELAYED ? 1 : 0};
 }
 
-int run(okpz_batch *b, int threads, int wgs, float *ms)
+int run(okpz_batch *b, int threads, int wgs, float *ms, uint64_t budget = 0,
+        int32_t *finished = nullptr)
 {
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     BHIP(hipEventRecord(e0, b->stream));
-    const Ring R = ring_of(b);
+    Ring R = ring_of(b);
+    R.budget = budget;
     hipError_t e = launch_any(R, threads, wgs);
     if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "batch launch: %s", hipGetErrorString(e));
     BHIP(hipEventRecord(e1, b->stream));
@@ -551,7 +569,7 @@ int run(okpz_batch *b, int threads, int wgs, float *ms)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (ms) *ms = t;
-    return check_control(R);
+    return check_control(R, finished);
 }
 
 }  // namespace
@@ -706,14 +724,58 @@ int okpz_batch_get_mapping(okpz_batch *b, int32_t *threads, int32_t *workgroups)
 int okpz_batch_run(okpz_batch *b)
 {
     if (!b) return bfail(OKPZ_EINVAL, "null batch");
+    int rc = okpz_batch_start(b);
+    if (rc != OKPZ_OK) return rc;
+    const int wgs = b->workgroups ? b->workgroups : 2 * b->cus;
+    rc = run(b, b->threads, wgs, &b->last_ms);
+    b->started = false;
+    if (rc == OKPZ_OK) b->ran = true;
+    return rc;
+}
+
+int okpz_batch_start(okpz_batch *b)
+{
+    if (!b) return bfail(OKPZ_EINVAL, "null batch");
     std::vector<int32_t> tmax(b->jobs.size());
     for (size_t r = 0; r < b->jobs.size(); ++r) tmax[r] = (int32_t)b->jobs[r].t_max;
     int rc = reset(b, tmax);
     if (rc != OKPZ_OK) return rc;
+    b->ran = false;
+    b->started = true;
+    b->last_ms = 0.f;
+    b->finished = 0;
+    return OKPZ_OK;
+}
+
+int okpz_batch_run_for(okpz_batch *b, double max_ms, int32_t *finished)
+{
+    if (!b) return bfail(OKPZ_EINVAL, "null batch");
+    if (!b->started) return bfail(OKPZ_EINVAL, "okpz_batch_start has not been called");
+    if (!(max_ms > 0.0) || max_ms > 3.6e6) return bfail(OKPZ_EINVAL, "max_ms must lie in (0, 3.6e6]");
+    if (b->tick_khz <= 0.0) {
+        int dev = 0, khz = 0;
+        BHIP(hipGetDevice(&dev));
+        BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        if (khz <= 0) return bfail(OKPZ_EDEVICE, "device reports no wall-clock rate");
+        b->tick_khz = khz;
+    }
+    const uint64_t budget = std::max<uint64_t>(1, (uint64_t)(max_ms * b->tick_khz));
     const int wgs = b->workgroups ? b->workgroups : 2 * b->cus;
-    rc = run(b, b->threads, wgs, &b->last_ms);
-    if (rc == OKPZ_OK) b->ran = true;
-    return rc;
+    float ms = 0.f;
+    int32_t done = 0;
+    int rc = run(b, b->threads, wgs, &ms, budget, &done);
+    b->last_ms += ms;
+    if (rc != OKPZ_OK) {
+        b->started = false;
+        return rc;
+    }
+    b->finished = done;
+    if (finished) *finished = done;
+    if (done == (int32_t)b->jobs.size()) {
+        b->started = false;
+        b->ran = true;
+    }
+    return OKPZ_OK;
 }
 
 int okpz_batch_last_ms(okpz_batch *b, float *ms)
@@ -757,6 +819,7 @@ int okpz_batch_autotune(okpz_batch *b, int64_t trial_mcs, int32_t *threads, int3
     b->threads = bt;
     b->workgroups = bw;
     b->ran = false;
+    b->started = false;
     if (threads) *threads = bt;
     if (workgroups) *workgroups = bw;
     return OKPZ_OK;

@@ -101,6 +101,8 @@ _sig("okpz_batch_set_mapping", ctypes.c_int, _vp, ctypes.c_int32, ctypes.c_int32
 _sig("okpz_batch_get_mapping", ctypes.c_int, _vp, _i32p, _i32p)
 _sig("okpz_batch_autotune", ctypes.c_int, _vp, _i64, _i32p, _i32p)
 _sig("okpz_batch_run", ctypes.c_int, _vp)
+_sig("okpz_batch_start", ctypes.c_int, _vp)
+_sig("okpz_batch_run_for", ctypes.c_int, _vp, ctypes.c_double, _i32p)
 _sig("okpz_batch_last_ms", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_float))
 _sig("okpz_batch_samples", ctypes.c_int, _vp, ctypes.c_int32, _i64p, _i64p, _i64p,
      ctypes.c_int32, _i32p)
@@ -139,7 +141,7 @@ EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_free", "okpz_last_error", "okpz_sampling_times", "okpz_batch_create",
             "okpz_batch_set_mapping",
             "okpz_batch_get_mapping", "okpz_batch_set_cell_borders",
-            "okpz_batch_get_cell_borders", "okpz_batch_autotune", "okpz_batch_run",
+            "okpz_batch_get_cell_borders", "okpz_batch_autotune", "okpz_batch_run", "okpz_batch_start", "okpz_batch_run_for",
             "okpz_batch_last_ms", "okpz_batch_samples", "okpz_batch_get_lattice", "okpz_batch_h0",
             "okpz_batch_w2_histogram", "okpz_batch_w2_cumulants", "okpz_batch_psi",
             "okpz_serve_create", "okpz_serve_set_mapping", "okpz_serve_set_cell_borders",
@@ -377,9 +379,22 @@ class Batch:
                                          ctypes.byref(w)))
         return t.value, w.value
 
-    def run(self) -> float:
-        """Run all jobs to t_max; returns the device time in ms."""
-        _bcheck(_lib.okpz_batch_run(self._h))
+    def run(self, slice_ms: float | None = None, progress=None) -> float:
+        """Run all jobs to t_max; returns the device time in ms.  With
+        slice_ms, the run goes in slices of about that many milliseconds
+        (okpz_batch_start / okpz_batch_run_for), calling progress(finished)
+        after each slice."""
+        if slice_ms is None:
+            _bcheck(_lib.okpz_batch_run(self._h))
+        else:
+            _bcheck(_lib.okpz_batch_start(self._h))
+            done = ctypes.c_int32(0)
+            while True:
+                _bcheck(_lib.okpz_batch_run_for(self._h, float(slice_ms), ctypes.byref(done)))
+                if progress is not None:
+                    progress(done.value)
+                if done.value == len(self.jobs):
+                    break
         ms = ctypes.c_float()
         _bcheck(_lib.okpz_batch_last_ms(self._h, ctypes.byref(ms)))
         return ms.value

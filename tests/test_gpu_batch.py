@@ -58,6 +58,27 @@ def test_batch_matches_jobs_run_alone(okpz):
     b.free()
 
 
+def test_sliced_run_equals_one_launch(okpz):
+    # the run in wall-clock slices (okpz_batch_start / okpz_batch_run_for):
+    # launches stop taking work mid-run and the next one continues; the
+    # results are those of the jobs alone, whatever the slice length
+    jobs = MIXED + [(1024, 1024, 1.0, 0.0, 31, 60), (512, 256, 0.95, 0.05, 32, 80)]
+    refs = [alone(okpz, j, M) for j in jobs]
+    for slice_ms in (0.05, 0.5, 5.0):
+        b = okpz.Batch(jobs, M)
+        seen = []
+        b.run(slice_ms=slice_ms, progress=seen.append)
+        assert seen[-1] == len(jobs) and seen == sorted(seen)
+        if slice_ms == 0.05:
+            assert len(seen) > 2, "the slices did not stop the launches early"
+        check_batch(okpz, b, jobs, M, refs)
+        b.free()
+    b = okpz.Batch(jobs, M)
+    with pytest.raises(okpz.OkpzError):
+        _ = okpz._bcheck(okpz._lib.okpz_batch_run_for(b._h, 1.0, None))
+    b.free()
+
+
 def test_batch_small_jobs_match_oracle(okpz):
     jobs = [(32, 32, 1.0, 0.0, 5, 12), (64, 96, 0.95, 0.05, 6, 8)]
     b = okpz.Batch(jobs, M)
