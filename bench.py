@@ -142,7 +142,9 @@ def batch_leg(scale, m=0.001, plain_scale=None):
     work = sum(L * L * t for L, _, _, _, _, t in jobs)
     b = okpz.Batch(jobs, m)
     t0 = time.perf_counter()
-    mapping = b.autotune(max(2, int(max(t for *_, t in jobs)) // 20))
+    # the trial runs the longest job 1/20 of its length, at most 20 000 MCS
+    # (six candidates: at most a few percent of a full-length run)
+    mapping = b.autotune(max(2, min(20000, int(max(t for *_, t in jobs)) // 20)))
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     if scale >= 0.05:
@@ -167,8 +169,9 @@ def batch_leg(scale, m=0.001, plain_scale=None):
     t_sat = int(2 * hist_L ** 1.6)
     t_from = t_sat if jobs[31][5] > t_sat else jobs[31][5] // 2
     regime = "steady state (t >= 2 L^1.6)" if t_from == t_sat else "growth regime (t < 2 L^1.6)"
-    counts, under, over = b.w2_histogram(hist_L, hist_L, t_from, 0.0, 20.0, 40)
     n_cum, _, kappa = b.w2_cumulants(hist_L, hist_L, t_from)
+    hist_hi = float(math.ceil(3.0 * kappa[0]))  # three times the mean W^2
+    counts, under, over = b.w2_histogram(hist_L, hist_L, t_from, 0.0, hist_hi, 40)
     b.free()
     if plain_scale is None:
         t0 = time.perf_counter()
@@ -203,7 +206,7 @@ def batch_leg(scale, m=0.001, plain_scale=None):
             "speedup_incl_autotune": plain_s / (batched_s + tune_s),
             "batched_site_updates_per_s": work / batched_s,
             "mapping": {"threads": mapping[0], "workgroups": mapping[1]},
-            "w2_histogram_L1024": {"t_from": t_from, "regime": regime, "lo": 0.0, "hi": 20.0,
+            "w2_histogram_L1024": {"t_from": t_from, "regime": regime, "lo": 0.0, "hi": hist_hi,
                                    "counts": counts.tolist(), "under": under, "over": over},
             "w2_cumulants_L1024": {"t_from": t_from, "regime": regime, "samples": n_cum,
                                    "kappa": kappa.tolist()}}
