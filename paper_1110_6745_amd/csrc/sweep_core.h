@@ -378,9 +378,18 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                     // 2 corner
                     const uint32_t ca = (h16 >> 10) & 7u, cb = h16 >> 13;
                     phs[j] = (uint32_t)(ca == 0u) + (uint32_t)(cb == 0u);
-                    const uint32_t ur = ox + cxo[j] + ca, vr = oy + cyo[j] + cb;
-                    off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
-                    sv[j] = smem[off[j] + Bx];  // current for the bulk phase only
+                    if (kFixedB == 256) {
+                        // row in the high half, column in the low half (no
+                        // carry between them); one byte permute takes both
+                        // mod 256 into (row << 8) | column
+                        const uint32_t Y = ((cb << 16) | ca) + ((cyo[j] << 16) | cxo[j]) +
+                                           ((oy << 16) | ox);
+                        off[j] = __builtin_amdgcn_perm(Y, Y, 0x0C0C0200u);
+                    } else {
+                        const uint32_t ur = ox + cxo[j] + ca, vr = oy + cyo[j] + cb;
+                        off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
+                    }
+                    sv[j] = smem[off[j] + Bx];
                     continue;
                 }
                 // Active site i = floor(49 h / 2^16) of the 7 x 7 (row-major),
@@ -431,13 +440,22 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                 // plain byte stores suffice there; an edge site and the edge
                 // site diagonally up and to the left of it (the next cell's
                 // bottom row) can share a neighbour byte, so edge flips are
-                // atomic XORs.  The bulk phase uses the site byte read above.
+                // atomic XORs (plain stores with atomics for that pair only
+                // measured slower: 30.8 against 26.4 ms at 2^17).
+                // Every phase uses the site byte read above: a site's own byte
+                // changes only by a move at the site, at its right neighbour
+                // or at its upper neighbour.  For a bulk site those are its
+                // own cell's sites or a later-phase site of the next cell
+                // (edge); for an edge site, its own cell's or the next
+                // cell's corner; for a corner, its own cell's.  A cell
+                // attempts one site per step, so no move of an earlier
+                // phase touches the byte of a later-phase site.
 #pragma unroll
                 for (int ph = 0; ph < 3; ++ph) {
 #pragma unroll
                     for (int j = 0; j < kCpt; ++j) {
                         if (phs[j] != (uint32_t)ph) continue;
-                        const uint32_t s0 = ph == 0 ? sv[j] : (uint32_t)smem[off[j] + Bx];
+                        const uint32_t s0 = sv[j];
                         if (s0 != 0u && (kMode == kGrowth || s0 != 0x1Bu)) continue;
                         const uint32_t l0 = smem[off[j] + Bx - 1];
                         const uint32_t d0 = smem[off[j]];

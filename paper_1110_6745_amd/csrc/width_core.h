@@ -72,29 +72,49 @@ __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
             for (int t = 0; t < kWpl; ++t)
                 if (t < nw) wd[t] = row[k0 + t];
         }
-        // heights relative to the first site of the lane's segment
-        int32_t B = 0, S1 = 0, S2 = 0, qrel = 0;
+        // heights relative to the first site of the lane's segment; every
+        // pass but the last has four words in every lane (a uniform test)
+        int32_t B = 0, S1 = 0, S2 = 0;
+        auto chunks = [&](uint32_t word) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t e = lut[(word >> (8 * j)) & 255u];
+                const int32_t s2 = (int32_t)(e & 0xffu);
+                const int32_t s1 = (int32_t)(int8_t)(e >> 8);
+                const int32_t d = (int32_t)(int8_t)(e >> 16);
+                const int32_t t1 = 8 * B + s1;
+                S1 += t1;
+                S2 += __mul24(B, t1 + s1) + s2;  // |B| <= 128: a 24-bit multiply
+                B += d;
+            }
+        };
+        if (base + 64 * kWpl <= v.W) {
+#pragma unroll
+            for (int t = 0; t < kWpl; ++t) chunks(wd[t]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < kWpl; ++t)
+                if (t < nw) chunks(wd[t]);
+        }
+        // Q(xs0): only in the pass holding word wq (a uniform test), and there
+        // only in the lane holding it
+        int32_t qrel = 0;
         bool hasq = false;
+        if (wq >= base && wq < base + 64 * kWpl) {
+            const int tq = wq - k0;
+            if (tq >= 0 && tq < kWpl) {
+                int32_t Bq = 0;
+                uint32_t word = wd[0];
 #pragma unroll
-        for (int t = 0; t < kWpl; ++t) {
-            if (t < nw) {
-                const uint32_t word = wd[t];
-                if (k0 + t == wq) {  // Q(xs0) inside this word
-                    const uint32_t below = bq ? (word & ((1u << bq) - 1u)) : 0u;
-                    qrel = B + 2 * (int32_t)__popc(below) - (int32_t)bq;
-                    hasq = true;
+                for (int t = 1; t < kWpl; ++t) {
+                    if (t <= tq) {
+                        Bq += 2 * (int32_t)__popc(wd[t - 1]) - 32;
+                        word = wd[t];
+                    }
                 }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t e = lut[(word >> (8 * j)) & 255u];
-                    const int32_t s2 = (int32_t)(e & 0xffu);
-                    const int32_t s1 = (int32_t)(int8_t)(e >> 8);
-                    const int32_t d = (int32_t)(int8_t)(e >> 16);
-                    const int32_t t1 = 8 * B + s1;
-                    S1 += t1;
-                    S2 += B * (t1 + s1) + s2;
-                    B += d;
-                }
+                const uint32_t below = bq ? (word & ((1u << bq) - 1u)) : 0u;
+                qrel = Bq + 2 * (int32_t)__popc(below) - (int32_t)bq;
+                hasq = true;
             }
         }
         int32_t incl = B;

@@ -21,8 +21,10 @@ from tests import inputs
 from tests.test_oracle_exact4x4 import _histogram_test
 
 
-def python_sweep(lat, p, q, seed, s, H0, delayed=True, phase_order=True):
-    """One tiled sweep written out directly from the contract."""
+def python_sweep(lat, p, q, seed, s, H0, delayed=True, phase_order=True, own_bonds=None):
+    """One tiled sweep written out directly from the contract.  With a list
+    ``own_bonds``, appends for every attempt whether the site's own two bonds
+    (sigma_x(x,y), sigma_y(x,y)) at its turn equal those at the step's start."""
     Ly, Lx = lat.shape
     Bx, By, C = oracle.geometry(Lx, Ly)
     key = (seed & 0xFFFFFFFF, seed >> 32)
@@ -60,10 +62,13 @@ def python_sweep(lat, p, q, seed, s, H0, delayed=True, phase_order=True):
                         a, b = 1 + idx % (C - 1), 1 + idx // (C - 1)
                     phase = int(a == 0) + int(b == 0) if phase_order else 0
                     picks.append((phase, c, (ox + cx * C + a) % Bx, (oy + cy * C + b) % By))
+                start = lat.copy() if own_bonds is not None else None
                 for _, c, u, v in sorted(picks):
                     if u == 0 or v == 0:
                         continue
                     X, Y = (x0 + u) % Lx, (y0 + v) % Ly
+                    if own_bonds is not None:
+                        own_bonds.append(int(lat[Y, X] & 3) == int(start[Y, X] & 3))
                     XL, YD = (X - 1) % Lx, (Y - 1) % Ly
                     slopes = (1 if lat[Y, XL] & 1 else -1, 1 if lat[Y, X] & 1 else -1,
                               1 if lat[YD, X] & 2 else -1, 1 if lat[Y, X] & 2 else -1)
@@ -95,6 +100,22 @@ def test_python_transcription_matches(Lx, Ly, delayed):
             Ha = oracle.sweep(a, p, q, seed, s, Ha, check=True, delayed=delayed)
             Hb = python_sweep(b, p, q, seed, s, Hb, delayed=delayed)
             assert np.array_equal(a, b) and Ha == Hb, (Lx, Ly, p, q, s)
+
+
+def test_no_earlier_phase_touches_a_later_site():
+    # A site's own bonds change only by a move at the site, at its right or at
+    # its upper neighbour; within a step those are in the site's own cell or
+    # are later-phase sites of the next cell, so every attempt sees its own
+    # bonds as they were at the step's start (the kernels read each site's
+    # byte once per step).  Checked on sweeps where moves of every phase
+    # happen, including blocks whose cell tiling wraps.
+    for (Lx, Ly), (p, q), seed in [((64, 64), (0.8, 0.6), 2), ((96, 48), (1.0, 0.0), 7),
+                                   ((32, 16), (0.5, 0.5), 11)]:
+        lat, H0 = inputs.rough_state(Lx, Ly, seed=seed, mcs=2)
+        seen = []
+        for s in range(4):
+            H0 = python_sweep(lat, p, q, seed, s, H0, delayed=True, own_bonds=seen)
+        assert len(seen) > 1000 and all(seen), (Lx, Ly)
 
 
 def test_phase_order_is_exercised():
