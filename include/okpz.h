@@ -328,15 +328,26 @@ int okpz_serve_submit(okpz_server *sv, const okpz_job *job, double arrival_s, in
 /* One quantum (admission, one launch, retirement).  Returns at once with
  * *running = 0 if nothing is resident. */
 int okpz_serve_step(okpz_server *sv, int32_t *running, int32_t *waiting);
-/* Job status (0 waiting, 1 running, 2 done) and its clock times (-1 if not yet). */
+/* Job status (0 waiting, 1 running, 2 done, 3 cancelled) and its clock
+ * times (-1 if not yet; a cancelled job's finish time is when it was
+ * cancelled). */
 int okpz_serve_job(okpz_server *sv, int64_t id, int32_t *state, double *arrival, double *admit,
                    double *finish);
-/* Samples of a finished job (as okpz_batch_samples). */
+/* Withdraw a job: a waiting job is never admitted; a running one is retired
+ * at once (between quanta), keeping the samples recorded so far, its H0 and,
+ * if it asked to keep it, its lattice at the MCS it had reached, and its
+ * device memory and slot are freed for other jobs.  Its state becomes 3.
+ * OKPZ_EINVAL for an unknown job or one that has finished or was cancelled. */
+int okpz_serve_cancel(okpz_server *sv, int64_t id);
+/* Samples of a finished job (as okpz_batch_samples); of a cancelled job,
+ * those recorded before the cancellation (count 0 if it never ran). */
 int okpz_serve_samples(okpz_server *sv, int64_t id, int64_t *t, int64_t *sum_h, int64_t *sum_h2,
                        int32_t cap, int32_t *count);
-/* Final H0 and, if kept, the canonical final lattice of a finished job. */
+/* Final H0 and, if kept, the canonical final lattice of a finished job (of a
+ * job cancelled while running: at the MCS it had reached). */
 int okpz_serve_result(okpz_server *sv, int64_t id, uint8_t *host, size_t bytes, int64_t *h0);
-/* Quanta run, device milliseconds, jobs done, device bytes held by jobs. */
+/* Quanta run, device milliseconds, jobs done (cancelled ones not counted), device bytes held
+ * by jobs. */
 int okpz_serve_stats(okpz_server *sv, int64_t *quanta, double *device_ms, int64_t *done,
                      size_t *bytes_in_use);
 int okpz_serve_free(okpz_server *sv);

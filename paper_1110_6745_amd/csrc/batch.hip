@@ -77,8 +77,8 @@ struct Control {
 // while the low word is below nitems[r] (its items per sweep).  A finished or empty job holds
 // kClosed in the low word.  A scan can see a word open that is exhausted or
 // closed by the time the wave's fetch-and-add lands; such late increments
-// are at most one per workgroup per word value, so the low word never
-// carries into the sweep number (kClosed + workgroups < 2^32).
+// are at most two (one claim) per workgroup per word value, so the low word
+// never carries into the sweep number (kClosed + 2 workgroups < 2^32).
 constexpr uint32_t kClosed = 0x80000000u;
 
 // Polled words (claim words, counters) are read and published at system
@@ -145,13 +145,42 @@ __device__ void publish(const JobDesc &jd, const JobState &ns, Control *ctl, uin
     __hip_atomic_store(&claim[r], (uint64_t)ns.s << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Wave 0 looks for an open item and claims one, trying jobs in priority
-// order (order[0] first).  Returns the job index and writes the claimed
-// (sweep << 32 | item), or -1.
+// Claim policy of a launch (flags):
+//   kClaimPairs: a workgroup takes two items of a job whose sweep has at
+//     least eight, so such a job still spreads over four or more workgroups
+//     while its claims and completion counts are halved;
+//   kClaimSticky: a workgroup first tries the job of its previous claim
+//     (one fetch-and-add, no scan of the claim words).
+// Ensembles use both (10 % faster on the finite-size-scaling mix); serving
+// uses neither: its quanta end with the slowest job's chain of sweeps, which
+// fewer workgroups per sweep lengthen (p50 and p99 latency rose with them).
+constexpr int32_t kClaimPairs = 1, kClaimSticky = 2;
+__device__ __forceinline__ int items_per_claim(int32_t nitems, int32_t flags)
+{
+    return (flags & kClaimPairs) && nitems >= 8 ? 2 : 1;
+}
+
+// Wave 0 looks for an open item and claims items_per_claim of them (fewer
+// if the sweep has fewer left): first of job `prefer` (the job of the
+// workgroup's previous claim, -1 for none) with one fetch-and-add and no
+// scan, else trying jobs in priority order (order[0] first).  Returns the
+// job index and writes the claimed (sweep << 32 | first item), or -1.
 __device__ int find_and_claim(uint64_t *claim, const int32_t *nitems, const int32_t *order,
-                              int njobs, uint64_t *got)
+                              int njobs, int prefer, int32_t flags, uint64_t *got)
 {
     const int lane = threadIdx.x & 63;
+    if (prefer >= 0 && (flags & kClaimSticky)) {
+        uint64_t w = 0;
+        if (lane == 0)
+            w = __hip_atomic_fetch_add(&claim[prefer],
+                                       (uint64_t)items_per_claim(nitems[prefer], flags),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        w = __shfl(w, 0, 64);
+        if ((uint32_t)w < (uint32_t)nitems[prefer]) {
+            *got = w;
+            return prefer;
+        }
+    }
     for (int base = 0; base < njobs; base += 64) {
         const int idx = base + lane;
         const int r = idx < njobs ? order[idx] : 0;
@@ -170,8 +199,8 @@ __device__ int find_and_claim(uint64_t *claim, const int32_t *nitems, const int3
             const int rr = __shfl(r, pick, 64);
             uint64_t w = 0;
             if (lane == 0)
-                w = __hip_atomic_fetch_add(&claim[rr], (uint64_t)1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                w = __hip_atomic_fetch_add(&claim[rr], (uint64_t)items_per_claim(nitems[rr], flags),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             w = __shfl(w, 0, 64);
             if ((uint32_t)w < (uint32_t)nitems[rr]) {
                 *got = w;
@@ -194,7 +223,8 @@ template <int kThreads, int kCells>
 __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const JobDesc *jobs, JobState *state,
                                                          Control *ctl, uint64_t *claim,
                                                          const int32_t *sched, int32_t njobs,
-                                                         uint64_t idle_limit, uint64_t budget)
+                                                         uint64_t idle_limit, uint64_t budget,
+                                                         int32_t claim_flags)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int s_job;     // >= 0: work; -1: exit; -2: retry
@@ -205,12 +235,14 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
     uint64_t idle = 0, seen = 0;
     const int32_t *nitems = sched, *order = sched + njobs;
     const uint64_t t_begin = budget ? (uint64_t)wall_clock64() : 0;
+    int last = -1;  // job of the previous claim (wave 0, uniform)
 
     while (true) {
         if (tid < 64) {
             uint64_t w = 0;
             const bool over = budget && (uint64_t)wall_clock64() - t_begin > budget;
-            int r = over ? -1 : find_and_claim(claim, nitems, order, njobs, &w);  // uniform over wave 0
+            int r = over ? -1 : find_and_claim(claim, nitems, order, njobs, last, claim_flags, &w);
+            if (r >= 0) last = r;
             if (tid == 0) {
                 if (over) {
                     r = -1;
@@ -253,7 +285,8 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
         const JobDesc jd = jobs[r];
         const JobState js = state[r];
         const SweepLaunch a = make_launch(jd, js);
-        const int g_end = min(jd.ngroups, (item + 1) * jd.chunk);
+        const int n_items = min(items_per_claim(jd.nitems, claim_flags), jd.nitems - item);
+        const int g_end = min(jd.ngroups, (item + n_items) * jd.chunk);
         for (int gi = item * jd.chunk; gi < g_end; ++gi) {
             const int b0 = gi * jd.G;
             const int Gc = min(jd.G, jd.nbx * jd.nby - b0);
@@ -268,10 +301,11 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
 
         if (tid == 0) {
             s_width = 0;
-            // release this item's lattice words; the last item acquires all
-            // (the increments form one release sequence)
-            const uint32_t d = __hip_atomic_fetch_add(&state[r].done, 1u, __ATOMIC_RELEASE,
-                                                      __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            // release these items' lattice words; the last item acquires
+            // all (the increments form one release sequence)
+            const uint32_t d = __hip_atomic_fetch_add(&state[r].done, (uint32_t)n_items,
+                                                      __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) +
+                               (uint32_t)n_items;
             if (d == (uint32_t)jd.nitems) {  // last item of sweep s: advance the job
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 JobState ns = js;
@@ -491,6 +525,7 @@ struct Ring {
     hipStream_t stream;
     int delayed_cells;  // 1: delayed thread-cell borders
     uint64_t budget = 0;  // wall-clock ticks per launch (0: run to the end)
+    int32_t claim_flags = 0;  // kClaimPairs | kClaimSticky for ensembles
 };
 
 template <int kThreads, int kCells>
@@ -509,7 +544,7 @@ hipError_t launch_ring(const Ring &R, int wgs)
     const uint64_t idle_limit = 1ull << 19;
     hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells>), dim3(wgs), dim3(kThreads),
                        okpz::core::kGroupLds, R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
-                       (int32_t)R.njobs, idle_limit, R.budget);
+                       (int32_t)R.njobs, idle_limit, R.budget, R.claim_flags);
     return hipGetLastError();
 }
 
@@ -560,6 +595,7 @@ int run(okpz_batch *b, int threads, int wgs, float *ms, uint64_t budget = 0,
     BHIP(hipEventRecord(e0, b->stream));
     Ring R = ring_of(b);
     R.budget = budget;
+    R.claim_flags = okpz::batch::kClaimPairs | okpz::batch::kClaimSticky;
     hipError_t e = launch_any(R, threads, wgs);
     if (e != hipSuccess) return bfail(OKPZ_EDEVICE, "batch launch: %s", hipGetErrorString(e));
     BHIP(hipEventRecord(e1, b->stream));
@@ -1038,7 +1074,7 @@ namespace {
 struct ServeJob {
     okpz_job job{};
     double arrival = 0, admit = -1, finish = -1;
-    int state = 0;  // 0 waiting, 1 running, 2 done
+    int state = 0;  // 0 waiting, 1 running, 2 done, 3 cancelled
     int slot = -1;
     bool keep_lattice = false;
     size_t bytes = 0;
@@ -1108,12 +1144,26 @@ double now_s(const okpz_server *s)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
 }
 
-int retire(okpz_server *sv, ServeJob &J, double t)
+// Retire a resident job: copy its samples (the first `nsamp` of them; all for
+// a finished job), H0 and, on request, its lattice to the host, free its
+// memory and its slot.  Called between quanta only (no device work of the
+// server is in flight then).
+int retire(okpz_server *sv, ServeJob &J, double t, bool cancelled = false)
 {
     const JobDesc &d = J.desc;
-    J.raw.assign(6 * (size_t)d.nsamp, 0);
-    if (d.nsamp)
-        BHIP(hipMemcpy(J.raw.data(), d.samples, 6 * 8 * (size_t)d.nsamp, hipMemcpyDeviceToHost));
+    int32_t nsamp = d.nsamp;
+    if (cancelled) {
+        if (J.grid) {
+            nsamp = J.next_sample;
+        } else {
+            JobState st;
+            BHIP(hipMemcpy(&st, sv->d_state + J.slot, sizeof st, hipMemcpyDeviceToHost));
+            nsamp = st.next_sample;
+        }
+    }
+    J.raw.assign(6 * (size_t)nsamp, 0);
+    if (nsamp)
+        BHIP(hipMemcpy(J.raw.data(), d.samples, 6 * 8 * (size_t)nsamp, hipMemcpyDeviceToHost));
     BHIP(hipMemcpy(&J.h0, d.h0, 8, hipMemcpyDeviceToHost));
     if (J.keep_lattice) {
         JobState st;
@@ -1138,9 +1188,9 @@ int retire(okpz_server *sv, ServeJob &J, double t)
     sv->used -= J.bytes;
     sv->slot_job[J.slot] = -1;
     J.slot = -1;
-    J.state = 2;
+    J.state = cancelled ? 3 : 2;
     J.finish = t;
-    ++sv->done;
+    if (!cancelled) ++sv->done;
     return OKPZ_OK;
 }
 
@@ -1523,14 +1573,37 @@ int okpz_serve_job(okpz_server *sv, int64_t id, int32_t *state, double *arrival,
     return OKPZ_OK;
 }
 
+int okpz_serve_cancel(okpz_server *sv, int64_t id)
+{
+    if (!sv) return bfail(OKPZ_EINVAL, "null server");
+    if (id < 0 || id >= (int64_t)sv->jobs.size()) return bfail(OKPZ_EINVAL, "unknown job");
+    ServeJob &J = sv->jobs[id];
+    const double t = now_s(sv);
+    if (J.state == 0) {
+        for (auto it = sv->waiting.begin(); it != sv->waiting.end(); ++it)
+            if (*it == id) {
+                sv->waiting.erase(it);
+                break;
+            }
+        J.raw.clear();
+        J.state = 3;
+        J.finish = t;
+        return OKPZ_OK;
+    }
+    if (J.state == 1) return retire(sv, J, t, true);
+    return bfail(OKPZ_EINVAL, "job %lld has already %s", (long long)id,
+                 J.state == 2 ? "finished" : "been cancelled");
+}
+
 int okpz_serve_samples(okpz_server *sv, int64_t id, int64_t *t, int64_t *sum_h, int64_t *sum_h2,
                        int32_t cap, int32_t *count)
 {
     if (!sv || !count) return bfail(OKPZ_EINVAL, "null argument");
     if (id < 0 || id >= (int64_t)sv->jobs.size()) return bfail(OKPZ_EINVAL, "unknown job");
     const ServeJob &J = sv->jobs[id];
-    if (J.state != 2) return bfail(OKPZ_EINVAL, "job %lld has not finished", (long long)id);
-    const int n = (int)J.times.size();
+    if (J.state != 2 && J.state != 3)
+        return bfail(OKPZ_EINVAL, "job %lld has not finished", (long long)id);
+    const int n = J.state == 2 ? (int)J.times.size() : (int)(J.raw.size() / 6);
     *count = n;
     if (!t && !sum_h && !sum_h2) return OKPZ_OK;
     if (cap < n) return bfail(OKPZ_EINVAL, "capacity %d < %d samples", cap, n);
@@ -1557,7 +1630,9 @@ int okpz_serve_result(okpz_server *sv, int64_t id, uint8_t *host, size_t bytes, 
     if (!sv) return bfail(OKPZ_EINVAL, "null server");
     if (id < 0 || id >= (int64_t)sv->jobs.size()) return bfail(OKPZ_EINVAL, "unknown job");
     const ServeJob &J = sv->jobs[id];
-    if (J.state != 2) return bfail(OKPZ_EINVAL, "job %lld has not finished", (long long)id);
+    if (J.state != 2 && !(J.state == 3 && J.admit >= 0))
+        return bfail(OKPZ_EINVAL, "job %lld has not finished (or was cancelled before it ran)",
+                     (long long)id);
     if (h0) *h0 = J.h0;
     if (host) {
         if (!J.keep_lattice) return bfail(OKPZ_EINVAL, "job %lld did not keep its lattice", (long long)id);

@@ -127,6 +127,7 @@ _sig("okpz_serve_submit", ctypes.c_int, _vp, _jobp, ctypes.c_double, ctypes.c_in
 _sig("okpz_serve_step", ctypes.c_int, _vp, _i32p, _i32p)
 _sig("okpz_serve_job", ctypes.c_int, _vp, _i64, _i32p, ctypes.POINTER(ctypes.c_double),
      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+_sig("okpz_serve_cancel", ctypes.c_int, _vp, _i64)
 _sig("okpz_serve_samples", ctypes.c_int, _vp, _i64, _i64p, _i64p, _i64p, ctypes.c_int32, _i32p)
 _sig("okpz_serve_result", ctypes.c_int, _vp, _i64, _u8p, _sz, _i64p)
 _sig("okpz_serve_stats", ctypes.c_int, _vp, _i64p, ctypes.POINTER(ctypes.c_double), _i64p,
@@ -147,7 +148,7 @@ EXPORTED = ["okpz_geometry", "okpz_required_bytes", "okpz_init", "okpz_init_on",
             "okpz_serve_create", "okpz_serve_set_mapping", "okpz_serve_set_cell_borders",
             "okpz_serve_get_cell_borders",
             "okpz_serve_now", "okpz_serve_submit", "okpz_serve_step", "okpz_serve_job",
-            "okpz_serve_samples", "okpz_serve_result", "okpz_serve_stats", "okpz_serve_free",
+            "okpz_serve_cancel", "okpz_serve_samples", "okpz_serve_result", "okpz_serve_stats", "okpz_serve_free",
             "okpz_batch_free", "okpz_batch_last_error"]
 
 
@@ -517,6 +518,11 @@ class Server:
         _bcheck(_lib.okpz_serve_job(self._h, i, ctypes.byref(st), ctypes.byref(a), ctypes.byref(b),
                                     ctypes.byref(c)))
         return {"state": st.value, "arrival": a.value, "admit": b.value, "finish": c.value}
+
+    def cancel(self, i: int) -> None:
+        """Withdraw job i (okpz_serve_cancel): never admitted if waiting,
+        retired at once with its samples so far if running."""
+        _bcheck(_lib.okpz_serve_cancel(self._h, int(i)))
 
     def samples(self, i: int):
         n = ctypes.c_int32()

@@ -173,3 +173,51 @@ def test_delayed_borders_equal_alone(okpz):
         sim.free()
         check_served(sv, i, job, m, delayed=True)
     sv.free()
+
+
+def test_cancel_waiting_and_running_jobs(okpz):
+    # a running job is retired at once with the samples it has so far (a
+    # prefix of its own run's), its lattice at the MCS it reached; a waiting
+    # job is never admitted; the other jobs are unaffected; a large job
+    # (plain sweep launches) can be cancelled the same way
+    m = 0.05
+    jobs = [(64, 64, 1.0, 0.0, 21, 400), (128, 128, 0.95, 0.05, 22, 300),
+            (4096, 4096, 1.0, 0.0, 23, 200), (32, 32, 0.6, 0.4, 24, 500),
+            (64, 64, 1.0, 0.0, 25, 80)]
+    sv = okpz.Server(hbm_budget=8 << 30, max_slots=8, quantum_sites=1 << 22, m=m)
+    ids = [sv.submit(j, -1.0, keep_lattice=True) for j in jobs[:4]]
+    late = sv.submit(jobs[4], sv.now() + 3600.0)  # arrives in an hour
+    for _ in range(15):  # one sweep per quantum each: past the first sampling time, 11
+        sv.step()
+    for i in (ids[1], ids[2]):
+        assert sv.job(i)["state"] == 1, "the job should be running"
+        sv.cancel(i)
+        assert sv.job(i)["state"] == 3
+    sv.cancel(late)
+    assert sv.job(late)["state"] == 3 and sv.samples(late)[0].size == 0
+    with pytest.raises(okpz.OkpzError):
+        sv.cancel(late)
+    with pytest.raises(okpz.OkpzError):
+        sv.result(late)
+    sv.drain(timeout_s=120.0)
+    for i, j in ((ids[0], jobs[0]), (ids[3], jobs[3])):
+        assert sv.job(i)["state"] == 2
+        check_served(sv, i, j, m)
+    for i in (ids[1], ids[2]):
+        Lx, Ly, p, q, seed, t_max = jobs[ids.index(i)]
+        t, s1, s2 = sv.samples(i)
+        ref, _, _ = alone(okpz, jobs[ids.index(i)], m)
+        got = list(zip(t.tolist(), s1.tolist(), s2.tolist()))
+        assert 0 < len(got) < len(ref) and got == ref[:len(got)], "samples are not a prefix"
+        g, gh0 = sv.result(i, lattice=True)
+        sim = okpz.okpz_init(Lx, Ly, p, q, seed)
+        sim.sweep(t[-1])
+        for _ in range(t_max - t[-1]):
+            if np.array_equal(sim.get_lattice(), g) and sim.h0() == gh0:
+                break
+            sim.sweep(1)
+        else:
+            raise AssertionError("the cancelled job's lattice is on no MCS of its run")
+        sim.free()
+    assert sv.stats()["done"] == 2
+    sv.free()
