@@ -44,6 +44,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+METRICS_PATH = None  # --metrics-jsonl: one JSON row per finished leg
+
+
+def metric_row(leg, fields):
+    """Append one row (wall-clock time, leg name and the leg's figures) to
+    the --metrics-jsonl file, when one was given."""
+    if METRICS_PATH is None:
+        return
+    row = {"time": time.time(), "leg": leg}
+    row.update(fields)
+    with open(METRICS_PATH, "a") as f:
+        f.write(json.dumps(row) + "\n")
+
+
 def single_core_rate(L, budget_s):
     """Oracle site updates/s of a flat L x L lattice (p = 1, q = 0, seed 1)
     on one host core, the paper's non-parallel reference point (Sec. II)."""
@@ -390,7 +404,11 @@ def main():
                     help="also run the 4096^2 workload (2 x 8 seeds, 10^4 MCS) as one batch")
     ap.add_argument("--w2-out", default=None,
                     help="write every width sample of the timed steps to this JSON file")
+    ap.add_argument("--metrics-jsonl", default=None,
+                    help="append one JSON row per finished leg to this file")
     args = ap.parse_args()
+    global METRICS_PATH
+    METRICS_PATH = args.metrics_jsonl
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent "
               "realizations shard trivially and one lattice is not split across GPUs here",
@@ -504,27 +522,43 @@ def main():
                       "S_direction_avg_n1_n2": [0.5 * (sx[1] + sy[1]), 0.5 * (sx[2] + sy[2])]}
         log(f"spectrum: {psd_ms:.3f} ms per call")
     log(f"sweep leg: {sweep_ms:.3f} ms per MCS, {value:.4g} site updates/s")
+    metric_row("sweep", {"L": L, "steps": args.steps, "ms_per_step": out["ms_per_step"],
+                         "sweep_kernel_ms": sweep_ms, "site_updates_per_s": value,
+                         "hbm_frac": out["roofline"]["frac"], "width_samples": len(widths)})
     if not args.no_cpu_baseline and args.cell_borders == "dead":
         out["cpu_baseline"] = cpu_baseline(okpz, sim, seed, p, q)
         log("cpu baseline done")
+        metric_row("cpu_baseline", {"site_updates_per_s": out["cpu_baseline"]["value"],
+                                    "cores": out["cpu_baseline"]["cores"],
+                                    "single_core": out["cpu_baseline"]["single_core"]["value"]})
     sim.free()
     del buf
     torch.cuda.synchronize()
     if args.delayed_steps > 0 and args.cell_borders == "dead" and not args.in_place:
         out["delayed_cells"] = delayed_leg(okpz, L, p, q, seed, args.delayed_steps)
         log(f"delayed-border leg: {out['delayed_cells']['sweep_kernel_ms']:.3f} ms per MCS")
+        metric_row("delayed_cells", {k: out["delayed_cells"][k]
+                                     for k in ("sweep_kernel_ms", "sweep_site_updates_per_s")})
     if args.size_scan:
         out["size_scan"] = size_scan(okpz, [1 << k for k in range(8, 17)])
         log("size scan done")
+        for r in out["size_scan"]:
+            metric_row("size_scan", r)
     if args.batch_scale > 0:
         out["batched_vs_plain"] = batch_leg(args.batch_scale, plain_scale=args.plain_scale)
         log(f"ensemble leg: speedup {out['batched_vs_plain']['speedup']:.3g}")
+        bp = out["batched_vs_plain"]
+        metric_row("ensemble", {k: bp[k] for k in ("scale", "batched_s", "autotune_s", "plain_s",
+                                                   "speedup", "batched_site_updates_per_s")})
     if args.medium:
         out["medium"] = medium_leg()
         log(f"medium leg: {out['medium']['seconds']:.2f} s")
+        metric_row("medium", {k: out["medium"][k] for k in ("seconds", "site_updates_per_s")})
     if args.serve_jobs > 0:
         out["serving"] = serve_leg(args.serve_jobs, 50.0)
         log("serving leg done")
+        for k in ("at_rate", "at_half_capacity"):
+            metric_row("serving_" + k, out["serving"][k])
     if "cpu_baseline" in out:
         one = out["cpu_baseline"]["single_core"]["value"]
         out["paper_context"] = {
