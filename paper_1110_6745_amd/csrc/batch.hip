@@ -121,12 +121,13 @@ __device__ inline SweepLaunch make_launch(const JobDesc &jd, const JobState &js)
 template <int kThreads, int kMode>
 __device__ __forceinline__ void run_group(const SweepLaunch &a, int b0, int G, uint8_t *smem)
 {
-    const int tiles = ((G * (a.By + 1) * a.Bx) + 15) & ~15;
-    uint32_t *opk = reinterpret_cast<uint32_t *>(smem + tiles);
+    uint32_t *opk = reinterpret_cast<uint32_t *>(smem + core::tile_bytes(a.Bx, a.By, G));
     if (a.Bx == core::kMaxB && a.By == core::kMaxB)
         core::sweep_group<kThreads, kMode, core::kMaxB, true>(a, b0, 1, smem, opk);
+    else if (a.Bx * a.By >= 64 * 64)  // a wave's cells share a block
+        core::sweep_group<kThreads, kMode, 0, true, false>(a, b0, G, smem, opk);
     else
-        core::sweep_group<kThreads, kMode, 0, true>(a, b0, G, smem, opk);
+        core::sweep_group<kThreads, kMode, 0, true, true>(a, b0, G, smem, opk);
 }
 
 // Publish job r's next sweep (or count it finished).  Thread 0 only, after
@@ -226,7 +227,8 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
                                                          uint64_t idle_limit, uint64_t budget,
                                                          int32_t claim_flags)
 {
-    extern __shared__ __align__(16) uint8_t smem[];
+    // static, so that the tile's base folds into the LDS instruction offsets
+    __shared__ __align__(16) uint8_t smem[okpz::core::kGroupLds];
     __shared__ int s_job;     // >= 0: work; -1: exit; -2: retry
     __shared__ uint64_t s_claim;
     __shared__ int s_width;   // 1: the job just reached a sampling time
@@ -531,19 +533,11 @@ struct Ring {
 template <int kThreads, int kCells>
 hipError_t launch_ring(const Ring &R, int wgs)
 {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)okpz::batch::batch_kernel<kThreads, kCells>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           okpz::core::kGroupLds);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     // about 2 s without any group completing anywhere (one probe: a scan of
     // the claim words plus a sleep of 16 x 64 cycles)
     const uint64_t idle_limit = 1ull << 19;
-    hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells>), dim3(wgs), dim3(kThreads),
-                       okpz::core::kGroupLds, R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
+    hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells>), dim3(wgs), dim3(kThreads), 0,
+                       R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
                        (int32_t)R.njobs, idle_limit, R.budget, R.claim_flags);
     return hipGetLastError();
 }

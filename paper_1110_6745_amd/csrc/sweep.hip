@@ -15,13 +15,13 @@ using core::kGrowth;
 // (blocks are independent within a sweep; the order does not matter).
 constexpr int kMaxGroupsPerLaunch = 1 << 21;
 
-template <int kThreads, int kMode, int kFixedB>
+template <int kThreads, int kMode, int kFixedB, bool kLaneOrg>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a, int G, int g0)
 {
-    // 256 x 256 blocks use a static tile (its base folds into the LDS
-    // instruction offsets); other block sides use dynamic LDS.
-    extern __shared__ __align__(16) uint8_t smem_dyn[];
-    __shared__ __align__(16) uint8_t smem_fix[kFixedB ? (kFixedB + 1) * kFixedB : 16];
+    // Static LDS, so that the tile's base folds into the LDS instruction
+    // offsets: one 256 x 256 block, or a group of smaller blocks with their
+    // origin and placement words.
+    __shared__ __align__(16) uint8_t smem_fix[kFixedB ? core::kPitch + kFixedB * core::kPitch : core::kGroupLds];
     __shared__ uint32_t opk_fix[kFixedB ? 32 : 1];
     const int nblk = a.ncol * a.nby;
     const int nl = gridDim.x;  // groups of this launch, starting at group g0
@@ -36,33 +36,22 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepLaunch a, int G, i
     if (kFixedB) {
         core::sweep_group<kThreads, kMode, kFixedB>(a, b0, 1, smem_fix, opk_fix);
     } else {
-        const int tiles = ((Gc * (a.By + 1) * a.Bx) + 15) & ~15;
-        core::sweep_group<kThreads, kMode, kFixedB>(
-            a, b0, Gc, smem_dyn, reinterpret_cast<uint32_t *>(smem_dyn + tiles));
+        const int tiles = core::tile_bytes(a.Bx, a.By, Gc);
+        core::sweep_group<kThreads, kMode, kFixedB, false, kLaneOrg>(
+            a, b0, Gc, smem_fix, reinterpret_cast<uint32_t *>(smem_fix + tiles));
     }
 }
 
-template <int kThreads, int kMode, int kFixedB>
+template <int kThreads, int kMode, int kFixedB, bool kLaneOrg>
 hipError_t launch_b(const SweepLaunch &a, hipStream_t st)
 {
     const int nblk = a.ncol * a.nby;
     const int G = kFixedB ? 1 : core::group_size(a.Bx, a.By, nblk);
     const int ngroups = (nblk + G - 1) / G;
-    const size_t lds = kFixedB ? 0
-                               : (size_t)(((G * (a.By + 1) * a.Bx) + 15) & ~15) + (size_t)G * 35 * 4;
-    static bool attr_set = false;
-    if (!attr_set && !kFixedB) {
-        // groups of up to ~74 KiB exceed the 64 KiB default of dynamic LDS
-        hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<kThreads, kMode, kFixedB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           core::kGroupLds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
     for (int g0 = 0; g0 < ngroups; g0 += kMaxGroupsPerLaunch) {
         const int n = ngroups - g0 < kMaxGroupsPerLaunch ? ngroups - g0 : kMaxGroupsPerLaunch;
-        hipLaunchKernelGGL((sweep_kernel<kThreads, kMode, kFixedB>), dim3(n), dim3(kThreads), lds, st,
-                           a, G, g0);
+        hipLaunchKernelGGL((sweep_kernel<kThreads, kMode, kFixedB, kLaneOrg>), dim3(n), dim3(kThreads), 0,
+                           st, a, G, g0);
     }
     return hipGetLastError();
 }
@@ -70,8 +59,10 @@ hipError_t launch_b(const SweepLaunch &a, hipStream_t st)
 template <int kThreads, int kMode>
 hipError_t launch_m(const SweepLaunch &a, hipStream_t st)
 {
-    if (a.Bx == core::kMaxB && a.By == core::kMaxB) return launch_b<kThreads, kMode, core::kMaxB>(a, st);
-    return launch_b<kThreads, kMode, 0>(a, st);
+    if (a.Bx == core::kMaxB && a.By == core::kMaxB) return launch_b<kThreads, kMode, core::kMaxB, false>(a, st);
+    // blocks of 64 cells or more: a wave's cells share a block
+    if (a.Bx * a.By >= 64 * 64) return launch_b<kThreads, kMode, 0, false>(a, st);
+    return launch_b<kThreads, kMode, 0, true>(a, st);
 }
 
 template <int kThreads, int kCells>

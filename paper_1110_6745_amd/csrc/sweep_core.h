@@ -37,6 +37,8 @@
 
 #include "okpz_internal.h"
 
+#include <type_traits>
+
 namespace okpz {
 namespace core {
 
@@ -44,9 +46,20 @@ constexpr int kMaxB = 256;
 constexpr int kCellsMax = (kMaxB / 8) * (kMaxB / 8);  // cells a workgroup holds
 constexpr int kSteps = 64;                             // C*C with C = 8
 constexpr int kMaxGroup = 64;                          // blocks per group (32 x 32)
-// LDS of a group: G tiles of (By + 1) x Bx bytes (one guard row each) with
-// G * Bx * By = 65536, plus 32 origin words and 3 placement words per block.
-constexpr int kGroupLds = 65536 + kMaxGroup * 32 + kMaxGroup * 32 * 4 + kMaxGroup * 3 * 4;
+constexpr int kPitch = 256;                            // bytes per LDS tile row
+// LDS tile of a group, for every block shape: a guard row, then rows of
+// kPitch bytes in bands of By rows, each band holding 256 / Bx blocks side by
+// side (block g in band g / (256 / Bx), column g mod (256 / Bx)).  Site (u, v)
+// of block g sits at byte kPitch + base(g) | v << 8 | u, so an attempt's three
+// bytes are one address plus the offsets 256, 255 and 0 whatever the block
+// size.  A full group fills the 256 x 256 sites (G Bx By = 65536).  After the
+// tile: 32 origin words and 3 placement words per block.
+__host__ __device__ inline int tile_bytes(int Bx, int By, int G)
+{
+    const int bpb = kPitch / Bx;
+    return kPitch + ((G + bpb - 1) / bpb) * By * kPitch;
+}
+constexpr int kGroupLds = kPitch + 65536 + kMaxGroup * 32 * 4 + kMaxGroup * 3 * 4;
 
 // Acceptance modes: p = 1, q = 0 (pure growth); p and q each 0 or 1;
 // general p, q (per-attempt acceptance draws).  kDelayedCells added to a
@@ -169,16 +182,43 @@ __device__ __forceinline__ void xor_byte(uint8_t *smem, uint32_t off, uint32_t v
     atomicXor(w, v << (8 * (off & 3u)));
 }
 
+// Origin of the cell grid in step 2m + odd of a block, from the block's
+// origin word m (x in byte 2 odd, y in byte 2 odd + 1): x << 16 and y << 16,
+// or (y << 16) | x.  A wave-uniform word (kUni) is unpacked with scalar
+// shifts; a per-lane word with one byte permute each.
+template <bool kUni>
+__device__ __forceinline__ uint32_t origin_x16(uint32_t w, int odd)
+{
+    if (kUni) return odd ? (w & 0x70000u) : ((w << 16) & 0x70000u);
+    return __builtin_amdgcn_perm(w, w, odd ? 0x0C020C0Cu : 0x0C000C0Cu);
+}
+template <bool kUni>
+__device__ __forceinline__ uint32_t origin_y16(uint32_t w, int odd)
+{
+    if (kUni) return odd ? ((w >> 8) & 0x70000u) : ((w << 8) & 0x70000u);
+    return __builtin_amdgcn_perm(w, w, odd ? 0x0C030C0Cu : 0x0C010C0Cu);
+}
+template <bool kUni>
+__device__ __forceinline__ uint32_t origin_yx(uint32_t w, int odd)
+{
+    if (kUni) return odd ? (((w >> 8) & 0x70000u) | ((w >> 16) & 7u)) : (((w << 8) & 0x70000u) | (w & 7u));
+    return __builtin_amdgcn_perm(w, w, odd ? 0x0C030C02u : 0x0C010C00u);
+}
+
 // One sweep of blocks [b0, b0 + G) of the lattice described by `a`.
-//   kFixedB = 256: 256 x 256 blocks, G = 1, static geometry (the three LDS
-//                  addresses of an attempt are one register plus offsets);
-//   kFixedB = 0:   any block sides 32..256, geometry from `a`.
-// smem: at least G * (By + 1) * Bx bytes; opk: G * 35 words of LDS (origins,
-// then the blocks' placement when kFixedB = 0).
+//   kFixedB = 256: 256 x 256 blocks, G = 1, static geometry;
+//   kFixedB = 0:   block sides 32..256 (powers of two), geometry from `a`.
+// Either way the three LDS addresses of an attempt are one register plus
+// offsets (the tile layout above).
+// kLaneOrg (kFixedB = 0 only): blocks of fewer than 64 cells, so that a
+// wave spans several blocks and each lane fetches its block's origins;
+// otherwise a wave's 64 cells share a block (Bx By >= 4096).
+// smem: at least tile_bytes(Bx, By, G) bytes; opk: G * 35 words of LDS
+// (origins, then the blocks' placement when kFixedB = 0).
 // kStoreThrough: write the new lattice with system-scope stores, which go
 // through to memory instead of staying dirty in this XCD's L2 (the persistent
 // kernel's hand-over to other XCDs then has little to write back).
-template <int kThreads, int kModeFull, int kFixedB, bool kStoreThrough = false>
+template <int kThreads, int kModeFull, int kFixedB, bool kStoreThrough = false, bool kLaneOrg = false>
 __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const int G,
                                             uint8_t *__restrict__ smem, uint32_t *opk)
 {
@@ -198,9 +238,15 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     asm volatile("" : "+v"(tid));
     const int Bx = a.Bx, By = a.By;
     const int wpr = Bx >> 5;
-    const int tsz = (By + 1) * Bx;  // bytes per tile incl. guard row
     const int lcpb = ilog2((uint32_t)((Bx >> 3) * (By >> 3)));
     const int ncx = Bx >> 3;
+    const int lwpr = ilog2((uint32_t)wpr), lby = ilog2((uint32_t)By);
+    const int lbpb = 8 - ilog2((uint32_t)Bx);  // 2^lbpb blocks side by side per band
+    // offset of block g's first row in the tile, after the guard row
+    auto tile_base = [&](int g) -> uint32_t {
+        if (kFixedB) return 0u;
+        return ((uint32_t)(g >> lbpb) << (8 + lby)) | ((uint32_t)(g & ((1 << lbpb) - 1)) << (8 - lbpb));
+    };
 
     // Block id of group member g.  Groups number the blocks of the launch:
     // all blocks in row-major order, or, for a lattice updated in place, the
@@ -214,19 +260,19 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     };
 
     // cell origins: one counter per pair of steps and block; word m of block
-    // g holds steps 2m and 2m+1 (three bits per coordinate).
+    // g holds step 2m in bytes 0 (x) and 1 (y), step 2m+1 in bytes 2 and 3
+    // (three bits each).
     for (int e = tid; e < G * (kSteps / 2); e += kThreads) {
         const int g = e >> 5, m = e & 31;
         const Ctr4 r = philox10_dev(Ctr4{a.s, (uint32_t)block_id(g), (uint32_t)m, kTagOrigin}, a.k0,
                                     a.k1);
-        opk[e] = (r.x >> 29) | ((r.y >> 29) << 3) | ((r.z >> 29) << 6) | ((r.w >> 29) << 9);
+        opk[e] = (r.x >> 29) | ((r.y >> 29) << 8) | ((r.z >> 29) << 16) | ((r.w >> 29) << 24);
     }
 
     // ---- block placement -------------------------------------------------
     // Block bid = block_id(g) starts at lattice site (sx + bi Bx, sy + bj By); that
     // column sits at stored column xs of the source copy.  Per block: xs, the
     // first row and bi (the block's word column in the destination copy).
-    const int lwpr = ilog2((uint32_t)wpr), lby = ilog2((uint32_t)By);
     auto place = [&](int g, int &xs, int &y0, int &bi) {
         const int bid = block_id(g);
         bi = bid % a.nbx;
@@ -251,10 +297,17 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     }
 
     // ---- HBM -> LDS with periodic wrap, bits -> bytes ---------------------
-    for (int e = tid; e < G * By * wpr; e += kThreads) {
-        const int k = e & (wpr - 1);
-        const int v = (e >> lwpr) & (By - 1);
-        const int g = kFixedB ? 0 : (e >> (lwpr + lby));
+    // Element e: tile row R = e >> 3 (band R >> lby, block row v = R mod By)
+    // and its 32-site piece c = e & 7 (block c >> lwpr of the band, word
+    // k = c mod wpr of the block row): consecutive lanes fill consecutive
+    // pieces of a tile row.
+    const int nrows = kFixedB ? kFixedB : (((G + (1 << lbpb) - 1) >> lbpb) << lby);
+    for (int e = tid; e < nrows * 8; e += kThreads) {
+        const int c = e & 7, R = e >> 3;
+        const int k = c & (wpr - 1);
+        const int v = R & (By - 1);
+        const int g = kFixedB ? 0 : (((R >> lby) << lbpb) | (c >> lwpr));
+        if (!kFixedB && g >= G) continue;  // the unused end of a last band
         const int xs = kFixedB ? fxs : geo[3 * g];
         int y = (kFixedB ? fy0 : geo[3 * g + 1]) + v;
         if (y >= a.Ly) y -= a.Ly;
@@ -281,7 +334,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
             for (int m = 0; m < 8; ++m) d[m] |= 0x04040404u;
         }
         if (k == 0) d[0] |= 4u;  // column u = 0 is the block border
-        uint4 *dst = reinterpret_cast<uint4 *>(smem + g * tsz + (v + 1) * Bx + 32 * k);
+        uint4 *dst = reinterpret_cast<uint4 *>(smem + kPitch + R * kPitch + 32 * c);
         dst[0] = uint4{d[0], d[1], d[2], d[3]};
         dst[1] = uint4{d[4], d[5], d[6], d[7]};
     }
@@ -292,15 +345,15 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     const bool has00 = (g00 >= 0 && g00 < G);  // uniform per workgroup
     int pre00 = 0;
     if (has00) {
-        if (tid == 0) pre00 = row_prefix_bx(smem + g00 * tsz + (a.v00 + 1) * Bx, a.u00);
+        if (tid == 0) pre00 = row_prefix_bx(smem + kPitch + tile_base(g00) + (a.v00 << 8), a.u00);
         __syncthreads();  // no step may flip that row before it is counted
     }
 
     // ---- the thread's cells ----------------------------------------------
     // A cell beyond the group gets zero masks and tile 0, so its site is
     // always (0,0) of block 0, a dead-border site: its attempt is a no-op.
-    const bool wave_in_block = lcpb >= 6;  // 64 lanes of a wave share a block
-    uint32_t cxo[kCpt], cyo[kCpt], mxj[kCpt], myj[kCpt], gbase[kCpt], cid[kCpt], bidj[kCpt];
+    const uint32_t mk = ((uint32_t)(By - 1) << 8) | (uint32_t)(Bx - 1);  // (v << 8) | u
+    uint32_t cxo[kCpt], cyo[kCpt], mkj[kCpt], gbase[kCpt], cid[kCpt], bidj[kCpt];
     uint32_t gj[kCpt];
     uint32_t opreg[kCpt];
 #pragma unroll
@@ -314,9 +367,8 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         // dead cell borders: the active sites start one in from the origin
         cxo[j] = (uint32_t)((c % ncx) * 8 + (kDelayed ? 0 : 1));
         cyo[j] = (uint32_t)((c / ncx) * 8 + (kDelayed ? 0 : 1));
-        mxj[j] = live ? (uint32_t)Bx - 1u : 0u;
-        myj[j] = live ? (uint32_t)By - 1u : 0u;
-        gbase[j] = live ? (uint32_t)(g * tsz) : 0u;
+        mkj[j] = live ? mk : 0u;
+        gbase[j] = live ? tile_base(g) : 0u;
         gj[j] = live ? (uint32_t)g : 0u;
         opreg[j] = opk[(live ? g : 0) * 32 + (tid & 31)];
     }
@@ -337,195 +389,199 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     uint32_t lv[kCpt], dv[kCpt];
 #pragma unroll
     for (int j = 0; j < kCpt; ++j) lv[j] = dv[j] = 0;
-    for (int gs = 0; gs < kSteps / 8; ++gs) {
-        Ctr4 nxt[kCpt];
-#pragma unroll
-        for (int j = 0; j < kCpt; ++j)
-            nxt[j] = Ctr4{a.s, bidj[j], ((uint32_t)(gs + 1) << 16) | cid[j], kTagSite};
-        uint32_t aw[kCpt][4];
+
+    // The 64 steps.  kUni: the 64 lanes of a wave share a block, so the
+    // origin words are read across lanes into scalar registers; otherwise
+    // each lane reads its block's word of the next step pair from LDS during
+    // the second step of the current pair.
+    auto run_steps = [&](auto uni) __attribute__((always_inline)) {
+        constexpr bool kUni = decltype(uni)::value;
         uint32_t opv[kCpt];
+        if (!kUni) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = gs * 8 + e;
-            if (kDrawAccept && (e & 3) == 0) {
+            for (int j = 0; j < kCpt; ++j) opv[j] = opk[gj[j] << 5];
+        }
+        for (int gs = 0; gs < kSteps / 8; ++gs) {
+            Ctr4 nxt[kCpt];
+#pragma unroll
+            for (int j = 0; j < kCpt; ++j)
+                nxt[j] = Ctr4{a.s, bidj[j], ((uint32_t)(gs + 1) << 16) | cid[j], kTagSite};
+            uint32_t aw[kCpt][4];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = gs * 8 + e;
+                if (kDrawAccept && (e & 3) == 0) {
+#pragma unroll
+                    for (int j = 0; j < kCpt; ++j) {
+                        const Ctr4 r = philox10_dev(
+                            Ctr4{a.s, bidj[j], ((uint32_t)(k >> 2) << 16) | cid[j], kTagAccept}, a.k0,
+                            a.k1);
+                        aw[j][0] = r.x; aw[j][1] = r.y; aw[j][2] = r.z; aw[j][3] = r.w;
+                    }
+                }
+                // all reads of the step first: the cells' byte sets are disjoint.
+                // For a site byte that is neither 0 nor 0x1B the low three bits
+                // of the site byte already rule out a move, whatever the
+                // neighbour bytes hold.
+                uint32_t off[kCpt], sv[kCpt], phs[kCpt];
 #pragma unroll
                 for (int j = 0; j < kCpt; ++j) {
-                    const Ctr4 r = philox10_dev(
-                        Ctr4{a.s, bidj[j], ((uint32_t)(k >> 2) << 16) | cid[j], kTagAccept}, a.k0,
-                        a.k1);
-                    aw[j][0] = r.x; aw[j][1] = r.y; aw[j][2] = r.z; aw[j][3] = r.w;
-                }
-            }
-            // all reads of the step first: the cells' byte sets are disjoint.
-            // For a site byte that is neither 0 nor 0x1B the low three bits
-            // of the site byte already rule out a move, whatever the
-            // neighbour bytes hold.
-            uint32_t off[kCpt], sv[kCpt], phs[kCpt];
-#pragma unroll
-            for (int j = 0; j < kCpt; ++j) {
-                if ((e & 1) == 0) {
-                    if (kFixedB || wave_in_block)
-                        opv[j] = (uint32_t)__builtin_amdgcn_readlane((int)opreg[j], k >> 1);
-                    else
-                        opv[j] = opk[(gj[j] << 5) + (k >> 1)];
-                }
-                const uint32_t op = opv[j] >> (6 * (e & 1));
-                const uint32_t ox = op & 7u, oy = (op >> 3) & 7u;
-                const uint32_t h16 = (e & 1) ? (sw[j][e >> 1] >> 16) : (sw[j][e >> 1] & 0xffffu);
-                if (kDelayed) {
-                    // site i = floor(64 h / 2^16) of the 8 x 8 cell: a = i mod 8,
-                    // b = i div 8; phase 0 bulk, 1 edge (one of a, b zero),
-                    // 2 corner
-                    const uint32_t ca = (h16 >> 10) & 7u, cb = h16 >> 13;
-                    phs[j] = (uint32_t)(ca == 0u) + (uint32_t)(cb == 0u);
-                    if (kFixedB == 256) {
+                    if (kUni && (e & 1) == 0) opv[j] = (uint32_t)__builtin_amdgcn_readlane((int)opreg[j], k >> 1);
+                    const uint32_t h16 = (e & 1) ? (sw[j][e >> 1] >> 16) : (sw[j][e >> 1] & 0xffffu);
+                    uint32_t o;
+                    if (kDelayed) {
+                        // site i = floor(64 h / 2^16) of the 8 x 8 cell: a = i mod 8,
+                        // b = i div 8; phase 0 bulk, 1 edge (one of a, b zero),
+                        // 2 corner
+                        const uint32_t ca = (h16 >> 10) & 7u, cb = h16 >> 13;
+                        phs[j] = (uint32_t)(ca == 0u) + (uint32_t)(cb == 0u);
                         // row in the high half, column in the low half (no
                         // carry between them); one byte permute takes both
                         // mod 256 into (row << 8) | column
                         const uint32_t Y = ((cb << 16) | ca) + ((cyo[j] << 16) | cxo[j]) +
-                                           ((oy << 16) | ox);
-                        off[j] = __builtin_amdgcn_perm(Y, Y, 0x0C0C0200u);
+                                           origin_yx<kUni>(opv[j], e & 1);
+                        o = __builtin_amdgcn_perm(Y, Y, 0x0C0C0200u);
                     } else {
-                        const uint32_t ur = ox + cxo[j] + ca, vr = oy + cyo[j] + cb;
-                        off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
+                        // Active site i = floor(49 h / 2^16) of the 7 x 7 (row-major),
+                        // split as i = 7 q + a without a division: with 7 h = q 2^16 + r,
+                        // q = floor(7 h / 2^16) = i div 7 and a = floor(7 r / 2^16) = i mod 7.
+                        // Y = 7 h + (row base << 16) keeps r in its low half, so
+                        // bits 16..23 of Y and X are the row and the column mod
+                        // 256; one byte permute packs them into (row << 8) | column
+                        const uint32_t Y = __umul24(h16, 7u) + (cyo[j] << 16) + origin_y16<kUni>(opv[j], e & 1);
+                        const uint32_t X =
+                            __umul24(Y & 0xffffu, 7u) + (cxo[j] << 16) + origin_x16<kUni>(opv[j], e & 1);
+                        o = __builtin_amdgcn_perm(Y, X, 0x0C0C0602u);
                     }
-                    sv[j] = smem[off[j] + Bx];
-                    continue;
+                    // smaller blocks: row and column mod the block sides, then
+                    // the block's place in the tile (disjoint bits)
+                    if (!kFixedB) o = (o & mkj[j]) | gbase[j];
+                    off[j] = o;
+                    sv[j] = smem[off[j] + kPitch];
+                    // behind the site read of a pair's second step: the next
+                    // pair's origin word (the last pair reads its own again)
+                    if (!kUni && (e & 1) == 1) opv[j] = opk[(gj[j] << 5) + min((k >> 1) + 1, kSteps / 2 - 1)];
                 }
-                // Active site i = floor(49 h / 2^16) of the 7 x 7 (row-major),
-                // split as i = 7 q + a without a division: with 7 h = q 2^16 + r,
-                // q = floor(7 h / 2^16) = i div 7 and a = floor(7 r / 2^16) = i mod 7.
-                if (kFixedB == 256) {
-                    // Y = 7 h + (row base << 16) keeps r in its low half, so
-                    // bits 16..23 of Y and X are the row and the column mod
-                    // 256; one byte permute packs them into (row << 8) | column
-                    const uint32_t Y = __umul24(h16, 7u) + (cyo[j] << 16) + (oy << 16);
-                    const uint32_t X = __umul24(Y & 0xffffu, 7u) + (cxo[j] << 16) + (ox << 16);
-                    off[j] = __builtin_amdgcn_perm(Y, X, 0x0C0C0602u);
-                } else {
-                    const uint32_t m7 = __umul24(h16, 7u);          // q in bits 16.., r below
-                    const uint32_t a7 = __umul24(m7 & 0xffffu, 7u);  // a in bits 16..18
-                    const uint32_t ur = ox + cxo[j] + (a7 >> 16);
-                    const uint32_t vr = oy + cyo[j] + (m7 >> 16);
-                    off[j] = gbase[j] + __umul24(vr & myj[j], (uint32_t)Bx) + (ur & mxj[j]);
-                }
-                sv[j] = smem[off[j] + Bx];
-            }
-            // While the reads are in flight: this step's share of the next
-            // Philox call, pinned here so that it is not sunk to its use.
-            // It is filler work: at low wave priority, so that waves whose
-            // step chain can go on (towards the step barrier) issue first.
-            __builtin_amdgcn_s_setprio(0);
-            if (gs + 1 < kSteps / 8) {
-#pragma unroll
-                for (int j = 0; j < kCpt; ++j) {
-                    switch (e) {  // rounds 0,1 | 1,2 | 2,3 | 3,5 | 5,6 | 6,7 | 7,8 | 8,10
-                    case 0: philox_rounds<0, 1>(nxt[j], a.k0, a.k1); break;
-                    case 1: philox_rounds<1, 2>(nxt[j], a.k0, a.k1); break;
-                    case 2: philox_rounds<2, 3>(nxt[j], a.k0, a.k1); break;
-                    case 3: philox_rounds<3, 5>(nxt[j], a.k0, a.k1); break;
-                    case 4: philox_rounds<5, 6>(nxt[j], a.k0, a.k1); break;
-                    case 5: philox_rounds<6, 7>(nxt[j], a.k0, a.k1); break;
-                    case 6: philox_rounds<7, 8>(nxt[j], a.k0, a.k1); break;
-                    default: philox_rounds<8, 10>(nxt[j], a.k0, a.k1); break;
-                    }
-                    asm volatile("" : "+v"(nxt[j].x), "+v"(nxt[j].y), "+v"(nxt[j].z), "+v"(nxt[j].w));
-                }
-            }
-            __builtin_amdgcn_s_setprio(2);
-            if (kDelayed) {
-                // Three phases.  Within one, attempted sites are never nearest
-                // neighbours.  Bulk sites are not diagonal neighbours either
-                // (as in the dead-border steps), and corners are 8 apart, so
-                // plain byte stores suffice there; an edge site and the edge
-                // site diagonally up and to the left of it (the next cell's
-                // bottom row) can share a neighbour byte, so edge flips are
-                // atomic XORs (plain stores with atomics for that pair only
-                // measured slower: 30.8 against 26.4 ms at 2^17).
-                // Every phase uses the site byte read above: a site's own byte
-                // changes only by a move at the site, at its right neighbour
-                // or at its upper neighbour.  For a bulk site those are its
-                // own cell's sites or a later-phase site of the next cell
-                // (edge); for an edge site, its own cell's or the next
-                // cell's corner; for a corner, its own cell's.  A cell
-                // attempts one site per step, so no move of an earlier
-                // phase touches the byte of a later-phase site.
-#pragma unroll
-                for (int ph = 0; ph < 3; ++ph) {
+                // While the reads are in flight: this step's share of the next
+                // Philox call, pinned here so that it is not sunk to its use.
+                // It is filler work: at low wave priority, so that waves whose
+                // step chain can go on (towards the step barrier) issue first.
+                __builtin_amdgcn_s_setprio(0);
+                if (gs + 1 < kSteps / 8) {
 #pragma unroll
                     for (int j = 0; j < kCpt; ++j) {
-                        if (phs[j] != (uint32_t)ph) continue;
-                        const uint32_t s0 = sv[j];
-                        if (s0 != 0u && (kMode == kGrowth || s0 != 0x1Bu)) continue;
-                        const uint32_t l0 = smem[off[j] + Bx - 1];
-                        const uint32_t d0 = smem[off[j]];
-                        const uint32_t r = kDrawAccept ? aw[j][e & 3] : 0u;
-                        if (!move_accepted<kMode>(s0, l0, d0, fixed_tbl, r, a.Tp, a.Tq)) continue;
-                        if (ph == 1) {
-                            xor_byte(smem, off[j] + Bx, 0x1Bu);
-                            xor_byte(smem, off[j] + Bx - 1, 0x09u);
-                            xor_byte(smem, off[j], 0x12u);
-                        } else {
-                            smem[off[j] + Bx] = (uint8_t)(s0 ^ 0x1Bu);
-                            smem[off[j] + Bx - 1] = (uint8_t)(l0 ^ 0x09u);
-                            smem[off[j]] = (uint8_t)(d0 ^ 0x12u);
+                        switch (e) {  // rounds 0,1 | 1,2 | 2,3 | 3,5 | 5,6 | 6,7 | 7,8 | 8,10
+                        case 0: philox_rounds<0, 1>(nxt[j], a.k0, a.k1); break;
+                        case 1: philox_rounds<1, 2>(nxt[j], a.k0, a.k1); break;
+                        case 2: philox_rounds<2, 3>(nxt[j], a.k0, a.k1); break;
+                        case 3: philox_rounds<3, 5>(nxt[j], a.k0, a.k1); break;
+                        case 4: philox_rounds<5, 6>(nxt[j], a.k0, a.k1); break;
+                        case 5: philox_rounds<6, 7>(nxt[j], a.k0, a.k1); break;
+                        case 6: philox_rounds<7, 8>(nxt[j], a.k0, a.k1); break;
+                        default: philox_rounds<8, 10>(nxt[j], a.k0, a.k1); break;
                         }
+                        asm volatile("" : "+v"(nxt[j].x), "+v"(nxt[j].y), "+v"(nxt[j].z), "+v"(nxt[j].w));
                     }
-                    __syncthreads();
                 }
-                continue;
+                __builtin_amdgcn_s_setprio(2);
+                if (kDelayed) {
+                    // Three phases.  Within one, attempted sites are never nearest
+                    // neighbours.  Bulk sites are not diagonal neighbours either
+                    // (as in the dead-border steps), and corners are 8 apart, so
+                    // plain byte stores suffice there; an edge site and the edge
+                    // site diagonally up and to the left of it (the next cell's
+                    // bottom row) can share a neighbour byte, so edge flips are
+                    // atomic XORs (plain stores with atomics for that pair only
+                    // measured slower: 30.8 against 26.4 ms at 2^17).
+                    // Every phase uses the site byte read above: a site's own byte
+                    // changes only by a move at the site, at its right neighbour
+                    // or at its upper neighbour.  For a bulk site those are its
+                    // own cell's sites or a later-phase site of the next cell
+                    // (edge); for an edge site, its own cell's or the next
+                    // cell's corner; for a corner, its own cell's.  A cell
+                    // attempts one site per step, so no move of an earlier
+                    // phase touches the byte of a later-phase site.
+#pragma unroll
+                    for (int ph = 0; ph < 3; ++ph) {
+#pragma unroll
+                        for (int j = 0; j < kCpt; ++j) {
+                            if (phs[j] != (uint32_t)ph) continue;
+                            const uint32_t s0 = sv[j];
+                            if (s0 != 0u && (kMode == kGrowth || s0 != 0x1Bu)) continue;
+                            const uint32_t l0 = smem[off[j] + kPitch - 1];
+                            const uint32_t d0 = smem[off[j]];
+                            const uint32_t r = kDrawAccept ? aw[j][e & 3] : 0u;
+                            if (!move_accepted<kMode>(s0, l0, d0, fixed_tbl, r, a.Tp, a.Tq)) continue;
+                            if (ph == 1) {
+                                xor_byte(smem, off[j] + kPitch, 0x1Bu);
+                                xor_byte(smem, off[j] + kPitch - 1, 0x09u);
+                                xor_byte(smem, off[j], 0x12u);
+                            } else {
+                                smem[off[j] + kPitch] = (uint8_t)(s0 ^ 0x1Bu);
+                                smem[off[j] + kPitch - 1] = (uint8_t)(l0 ^ 0x09u);
+                                smem[off[j]] = (uint8_t)(d0 ^ 0x12u);
+                            }
+                        }
+                        __syncthreads();
+                    }
+                    continue;
+                }
+#pragma unroll
+                for (int j = 0; j < kCpt; ++j) {
+                    // the loads zero-extend; keep the code generator from
+                    // re-narrowing the bytes (it would add masking operations)
+                    asm volatile("" : "+v"(sv[j]));
+                    // Only a site at a local minimum (byte 0) or maximum (0x1B)
+                    // can move; only those lanes read the two neighbour bytes,
+                    // which roughly halves the LDS read traffic of a step.
+                    const bool cand = (sv[j] == 0u) || (kMode != kGrowth && sv[j] == 0x1Bu);
+                    if (cand) {
+                        lv[j] = smem[off[j] + kPitch - 1];
+                        dv[j] = smem[off[j]];
+                    }
+                    asm volatile("" : "+v"(lv[j]), "+v"(dv[j]));
+                }
+#pragma unroll
+                for (int j = 0; j < kCpt; ++j) {
+                    const uint32_t r = kDrawAccept ? aw[j][e & 3] : 0u;
+                    if (move_accepted<kMode>(sv[j], lv[j], dv[j], fixed_tbl, r, a.Tp, a.Tq)) {
+                        // a growth flip only ever turns 0 (minimum) into 0x1B
+                        smem[off[j] + kPitch] = (kMode == kGrowth) ? (uint8_t)0x1Bu : (uint8_t)(sv[j] ^ 0x1Bu);
+                        smem[off[j] + kPitch - 1] = (uint8_t)(lv[j] ^ 0x09u);
+                        smem[off[j]] = (uint8_t)(dv[j] ^ 0x12u);
+                    }
+                }
+                __syncthreads();
             }
 #pragma unroll
             for (int j = 0; j < kCpt; ++j) {
-                // the loads zero-extend; keep the code generator from
-                // re-narrowing the bytes (it would add masking operations)
-                asm volatile("" : "+v"(sv[j]));
-                // Only a site at a local minimum (byte 0) or maximum (0x1B)
-                // can move; only those lanes read the two neighbour bytes,
-                // which roughly halves the LDS read traffic of a step.
-                const bool cand = (sv[j] == 0u) || (kMode != kGrowth && sv[j] == 0x1Bu);
-                if (cand) {
-                    lv[j] = smem[off[j] + Bx - 1];
-                    dv[j] = smem[off[j]];
-                }
-                asm volatile("" : "+v"(lv[j]), "+v"(dv[j]));
+                sw[j][0] = nxt[j].x; sw[j][1] = nxt[j].y; sw[j][2] = nxt[j].z; sw[j][3] = nxt[j].w;
             }
-#pragma unroll
-            for (int j = 0; j < kCpt; ++j) {
-                const uint32_t r = kDrawAccept ? aw[j][e & 3] : 0u;
-                if (move_accepted<kMode>(sv[j], lv[j], dv[j], fixed_tbl, r, a.Tp, a.Tq)) {
-                    // a growth flip only ever turns 0 (minimum) into 0x1B
-                    smem[off[j] + Bx] = (kMode == kGrowth) ? (uint8_t)0x1Bu : (uint8_t)(sv[j] ^ 0x1Bu);
-                    smem[off[j] + Bx - 1] = (uint8_t)(lv[j] ^ 0x09u);
-                    smem[off[j]] = (uint8_t)(dv[j] ^ 0x12u);
-                }
-            }
-            __syncthreads();
         }
-#pragma unroll
-        for (int j = 0; j < kCpt; ++j) {
-            sw[j][0] = nxt[j].x; sw[j][1] = nxt[j].y; sw[j][2] = nxt[j].z; sw[j][3] = nxt[j].w;
-        }
-    }
+    };
+    run_steps(std::integral_constant<bool, kFixedB != 0 || !kLaneOrg>{});
 
     // the store below is not on any step's critical path: back to low
     // priority, behind the steps of a co-resident workgroup
     __builtin_amdgcn_s_setprio(0);
 
     if (has00 && tid == 0) {
-        const int post00 = row_prefix_bx(smem + g00 * tsz + (a.v00 + 1) * Bx, a.u00);
+        const int post00 = row_prefix_bx(smem + kPitch + tile_base(g00) + (a.v00 << 8), a.u00);
         *a.h0 += 2 * (int64_t)(post00 - pre00);
     }
 
     // ---- LDS -> HBM: bytes -> bits, aligned into the other copy -----------
-    for (int e = tid; e < G * By * wpr; e += kThreads) {
-        const int k = e & (wpr - 1);
-        const int v = (e >> lwpr) & (By - 1);
-        const int g = kFixedB ? 0 : (e >> (lwpr + lby));
+    // (elements as in the load above)
+    for (int e = tid; e < nrows * 8; e += kThreads) {
+        const int c = e & 7, R = e >> 3;
+        const int k = c & (wpr - 1);
+        const int v = R & (By - 1);
+        const int g = kFixedB ? 0 : (((R >> lby) << lbpb) | (c >> lwpr));
+        if (!kFixedB && g >= G) continue;
         const int bi = kFixedB ? fbi : geo[3 * g + 2];
         int y = (kFixedB ? fy0 : geo[3 * g + 1]) + v;
         if (y >= a.Ly) y -= a.Ly;
-        const uint4 *src = reinterpret_cast<const uint4 *>(smem + g * tsz + (v + 1) * Bx + 32 * k);
+        const uint4 *src = reinterpret_cast<const uint4 *>(smem + kPitch + R * kPitch + 32 * c);
         const uint4 q0 = src[0], q1 = src[1];
         const uint32_t d[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
         uint32_t bxw = 0, byw = 0;
