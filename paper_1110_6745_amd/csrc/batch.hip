@@ -214,13 +214,15 @@ __device__ int find_and_claim(uint64_t *claim, const int32_t *nitems, const int3
 }
 
 // kCells: 0 for dead thread-cell borders, core::kDelayedCells for delayed
-// ones (one kind per launch).
+// ones (one kind per launch).  kGrowthOnly: every job runs p = 1, q = 0, so
+// only that acceptance mode's sweep bodies are compiled in (fewer registers:
+// at 1024 threads the kernel then keeps its step loops free of spills).
 // budget: wall-clock ticks (wall_clock64) after which a workgroup stops
 // claiming new items and exits; 0 runs until every job has finished.  An
 // item once claimed is always completed, so a launch that stops early leaves
 // every job at a consistent point (its open items stay claimable) and the
 // next launch over the same tables continues where it stopped.
-template <int kThreads, int kCells>
+template <int kThreads, int kCells, bool kGrowthOnly>
 __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const JobDesc *jobs, JobState *state,
                                                          Control *ctl, uint64_t *claim,
                                                          const int32_t *sched, int32_t njobs,
@@ -292,12 +294,14 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
         for (int gi = item * jd.chunk; gi < g_end; ++gi) {
             const int b0 = gi * jd.G;
             const int Gc = min(jd.G, jd.nbx * jd.nby - b0);
-            if (jd.mode == core::kGrowth)
+            if (kGrowthOnly || jd.mode == core::kGrowth)
                 run_group<kThreads, core::kGrowth | kCells>(a, b0, Gc, smem);
-            else if (jd.mode == core::kFixed)
-                run_group<kThreads, core::kFixed | kCells>(a, b0, Gc, smem);
-            else
-                run_group<kThreads, core::kDraw | kCells>(a, b0, Gc, smem);
+            else if constexpr (!kGrowthOnly) {
+                if (jd.mode == core::kFixed)
+                    run_group<kThreads, core::kFixed | kCells>(a, b0, Gc, smem);
+                else
+                    run_group<kThreads, core::kDraw | kCells>(a, b0, Gc, smem);
+            }
             __syncthreads();  // the group's tile is reused by the next group
         }
 
@@ -331,7 +335,9 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
             uint32_t *lut = reinterpret_cast<uint32_t *>(smem + 20 * 1024);
             core::width_lut_build(lut);
             __syncthreads();
-            for (int y = wave; y < jd.Ly; y += nwave) core::width_row(v, y, lane, lut, jd.rows);
+            // one word per lane: the narrow form keeps the kernel's registers
+            // down (a 1024 x 1024 lattice's rows are 32 words, one pass)
+            for (int y = wave; y < jd.Ly; y += nwave) core::width_row<1>(v, y, lane, lut, jd.rows);
             __syncthreads();  // rows are read back by other waves of this workgroup (same CU)
             core::width_combine(jd.rows, jd.Lx, jd.Ly, s_out, reinterpret_cast<int64_t *>(smem));
             if (tid == 0) {
@@ -528,6 +534,7 @@ struct Ring {
     int delayed_cells;  // 1: delayed thread-cell borders
     uint64_t budget = 0;  // wall-clock ticks per launch (0: run to the end)
     int32_t claim_flags = 0;  // kClaimPairs | kClaimSticky for ensembles
+    int growth_only = 0;  // 1: every job runs p = 1, q = 0
 };
 
 template <int kThreads, int kCells>
@@ -536,9 +543,14 @@ hipError_t launch_ring(const Ring &R, int wgs)
     // about 2 s without any group completing anywhere (one probe: a scan of
     // the claim words plus a sleep of 16 x 64 cycles)
     const uint64_t idle_limit = 1ull << 19;
-    hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells>), dim3(wgs), dim3(kThreads), 0,
-                       R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
-                       (int32_t)R.njobs, idle_limit, R.budget, R.claim_flags);
+    if (R.growth_only)
+        hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells, true>), dim3(wgs), dim3(kThreads),
+                           0, R.stream, R.desc, R.state, R.ctl, R.claim, R.sched, (int32_t)R.njobs,
+                           idle_limit, R.budget, R.claim_flags);
+    else
+        hipLaunchKernelGGL((okpz::batch::batch_kernel<kThreads, kCells, false>), dim3(wgs),
+                           dim3(kThreads), 0, R.stream, R.desc, R.state, R.ctl, R.claim, R.sched,
+                           (int32_t)R.njobs, idle_limit, R.budget, R.claim_flags);
     return hipGetLastError();
 }
 
@@ -576,8 +588,11 @@ int check_control(const Ring &R, int32_t *finished = nullptr)
 
 Ring ring_of(okpz_batch *b)
 {
-    return Ring{b->d_desc, b->d_state, b->d_ctl, b->d_claim, b->d_sched, (int)b->jobs.size(), b->stream,
-                b->cell_borders == OKPZ_CELLS_DELAYED ? 1 : 0};
+    Ring R{b->d_desc, b->d_state, b->d_ctl, b->d_claim, b->d_sched, (int)b->jobs.size(), b->stream,
+           b->cell_borders == OKPZ_CELLS_DELAYED ? 1 : 0};
+    R.growth_only = 1;
+    for (const auto &d : b->desc) R.growth_only &= d.mode == okpz::core::kGrowth ? 1 : 0;
+    return R;
 }
 
 int run(okpz_batch *b, int threads, int wgs, float *ms, uint64_t budget = 0,

@@ -42,16 +42,17 @@ __device__ __forceinline__ void width_lut_build(uint32_t *lut)
 // writes rows[y] = sum_x P, rows[Ly + y] = sum_x P^2, rows[2 Ly + y] = the
 // sigma_y bit at physical column 0.  lut: the chunk table in LDS.
 //
-// The row is read in stored order, four aligned words per lane per pass.
+// The row is read in stored order, kWpl words per lane per pass (four: one
+// aligned 16-byte load; one for narrow rows, with fewer registers).
 // With Q(c) the sigma_x prefix over stored columns c' < c and xs0 the stored
 // column of physical column 0, the full row sums to zero (a periodic row), so
 // P(x) = Q((xs0 + x) mod Lx) - Q(xs0) for every x; the physical sums follow
 // from the stored-order ones:
 //   sum P = sum Q - Lx Q(xs0),  sum P^2 = sum Q^2 - 2 Q(xs0) sum Q + Lx Q(xs0)^2.
+template <int kWpl = 4>
 __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
                                          const uint32_t *lut, int64_t *rows)
 {
-    constexpr int kWpl = 4;
     const uint32_t *row = v.planes + (size_t)y * v.W;
     const int xs0 = (v.Lx - v.ox) % v.Lx;  // stored column of physical column 0
     const int wq = xs0 >> 5;
@@ -63,8 +64,10 @@ __device__ __forceinline__ void width_row(const LatticeView &v, int y, int lane,
     for (int base = 0; base < v.W; base += 64 * kWpl) {
         const int k0 = base + lane * kWpl;
         const int nw = max(0, min(kWpl, v.W - k0));  // words of this lane
-        uint32_t wd[kWpl] = {0u, 0u, 0u, 0u};
-        if (vec && nw == kWpl) {
+        uint32_t wd[kWpl];
+#pragma unroll
+        for (int t = 0; t < kWpl; ++t) wd[t] = 0u;
+        if (kWpl == 4 && vec && nw == kWpl) {
             const uint4 q = *reinterpret_cast<const uint4 *>(row + k0);
             wd[0] = q.x; wd[1] = q.y; wd[2] = q.z; wd[3] = q.w;
         } else {
