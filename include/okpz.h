@@ -221,7 +221,8 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
 
 /* Execution mapping of the persistent launch: threads per workgroup (256,
  * 512, 1024) and resident workgroups (0 = two per compute unit).  Results do
- * not depend on it. */
+ * not depend on it.  Default: 1024 threads when every job has p = 1, q = 0,
+ * else 512; two workgroups per compute unit. */
 int okpz_batch_set_mapping(okpz_batch *b, int32_t threads, int32_t workgroups);
 int okpz_batch_get_mapping(okpz_batch *b, int32_t *threads, int32_t *workgroups);
 

@@ -418,7 +418,7 @@ struct okpz_batch {
     Control *d_ctl = nullptr;
     uint64_t *d_claim = nullptr;
     int32_t *d_sched = nullptr;
-    int threads = 512;  // two workgroups per CU without spills
+    int threads = 512;  // two workgroups per CU (1024 for growth-only tables, set at creation)
     int workgroups = 0;  // 0: two per compute unit
     int cus = 0;
     hipStream_t stream = nullptr;
@@ -721,6 +721,11 @@ int okpz_batch_create(okpz_batch **out, const okpz_job *jobs, int32_t n_jobs, do
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (b->cus <= 0) b->cus = 256;
+    // an all-(1, 0) table runs the growth-only kernel, whose step loops stay
+    // free of spills at 1024 threads and two workgroups per CU
+    bool growth = true;
+    for (const auto &d : b->desc) growth = growth && d.mode == okpz::core::kGrowth;
+    if (growth) b->threads = 1024;
     e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipFree(b->mem);
