@@ -125,6 +125,32 @@ def test_mapping_does_not_change_results(okpz, threads, wgs):
     b.free()
 
 
+GROWTH = [(Lx, Ly, 1.0, 0.0, seed, t) for (Lx, Ly, _, _, seed, t) in MIXED]
+
+
+@pytest.mark.parametrize("cells", [0, 1])
+@pytest.mark.parametrize("threads,wgs", [(256, 0), (512, 0), (1024, 0), (1024, 9)])
+def test_growth_only_table(okpz, threads, wgs, cells):
+    # every job p = 1, q = 0: the launch runs the growth-only kernel; the same
+    # shapes as MIXED (every block size, partial bands and groups), each job
+    # bit for bit its lone trajectory, for every mapping and both borders
+    D = okpz.OKPZ_CELLS_DELAYED if cells else okpz.OKPZ_CELLS_DEAD
+    refs = [alone(okpz, j, M, D) for j in GROWTH]
+    b = okpz.Batch(GROWTH, M)
+    assert b.mapping()[0] == 1024  # the default for growth-only tables
+    b.set_cell_borders(D)
+    b.set_mapping(threads, wgs)
+    b.run()
+    check_batch(okpz, b, GROWTH, M, refs)
+    b.free()
+
+
+def test_default_mapping_of_mixed_tables(okpz):
+    b = okpz.Batch(MIXED[:4], M)
+    assert b.mapping()[0] == 512
+    b.free()
+
+
 def test_many_tiny_jobs(okpz):
     jobs = [(32 * (1 + r % 4), 32, 1.0 if r % 2 else 0.9, 0.0 if r % 3 else 0.1, 100 + r,
              5 + r % 17) for r in range(300)]
