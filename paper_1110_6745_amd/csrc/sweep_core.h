@@ -53,13 +53,14 @@ constexpr int kPitch = 256;                            // bytes per LDS tile row
 // of block g sits at byte kPitch + base(g) | v << 8 | u, so an attempt's three
 // bytes are one address plus the offsets 256, 255 and 0 whatever the block
 // size.  A full group fills the 256 x 256 sites (G Bx By = 65536).  After the
-// tile: 32 origin words and 3 placement words per block.
+// tile: 33 origin words (32 used; the pad puts the words of consecutive blocks
+// in different LDS banks) and 3 placement words per block.
 __host__ __device__ inline int tile_bytes(int Bx, int By, int G)
 {
     const int bpb = kPitch / Bx;
     return kPitch + ((G + bpb - 1) / bpb) * By * kPitch;
 }
-constexpr int kGroupLds = kPitch + 65536 + kMaxGroup * 32 * 4 + kMaxGroup * 3 * 4;
+constexpr int kGroupLds = kPitch + 65536 + kMaxGroup * 33 * 4 + kMaxGroup * 3 * 4;
 
 // Acceptance modes: p = 1, q = 0 (pure growth); p and q each 0 or 1;
 // general p, q (per-attempt acceptance draws).  kDelayedCells added to a
@@ -213,7 +214,7 @@ __device__ __forceinline__ uint32_t origin_yx(uint32_t w, int odd)
 // kLaneOrg (kFixedB = 0 only): blocks of fewer than 64 cells, so that a
 // wave spans several blocks and each lane fetches its block's origins;
 // otherwise a wave's 64 cells share a block (Bx By >= 4096).
-// smem: at least tile_bytes(Bx, By, G) bytes; opk: G * 35 words of LDS
+// smem: at least tile_bytes(Bx, By, G) bytes; opk: G * 36 words of LDS
 // (origins, then the blocks' placement when kFixedB = 0).
 // kStoreThrough: write the new lattice with system-scope stores, which go
 // through to memory instead of staying dirty in this XCD's L2 (the persistent
@@ -227,6 +228,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
     constexpr bool kOneCopy = (kModeFull & kInPlace) != 0;
     constexpr bool kDrawAccept = (kMode == kDraw);
     constexpr int kCpt = kCellsMax / kThreads;
+    constexpr int kOpkStride = kFixedB ? 32 : 33;  // origin words per block (one block: no pad)
     if (kFixedB) {
         a.Bx = kFixedB;
         a.By = kFixedB;
@@ -266,7 +268,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         const int g = e >> 5, m = e & 31;
         const Ctr4 r = philox10_dev(Ctr4{a.s, (uint32_t)block_id(g), (uint32_t)m, kTagOrigin}, a.k0,
                                     a.k1);
-        opk[e] = (r.x >> 29) | ((r.y >> 29) << 8) | ((r.z >> 29) << 16) | ((r.w >> 29) << 24);
+        opk[(e >> 5) * kOpkStride + (e & 31)] = (r.x >> 29) | ((r.y >> 29) << 8) | ((r.z >> 29) << 16) | ((r.w >> 29) << 24);
     }
 
     // ---- block placement -------------------------------------------------
@@ -282,7 +284,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         y0 = a.sy + bj * By;
     };
     int fxs = 0, fy0 = 0, fbi = 0;
-    int *geo = reinterpret_cast<int *>(opk + G * 32);
+    int *geo = reinterpret_cast<int *>(opk + G * kOpkStride);
     if (kFixedB) {
         place(0, fxs, fy0, fbi);
     } else {
@@ -359,8 +361,22 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
 #pragma unroll
     for (int j = 0; j < kCpt; ++j) {
         const int q = tid + j * kThreads;
-        const int g = q >> lcpb;
-        const int c = q & ((1 << lcpb) - 1);
+        int g, c;
+        if (kLaneOrg) {
+            // blocks under 64 cells: cell q at column q mod 32 and row q / 32
+            // of the tile's 32 x 32 cells, as in one 256 x 256 block, so that
+            // a wave's 64 cells span a whole tile row (all LDS banks) instead
+            // of four neighbouring blocks (half the banks); with the origin
+            // words padded to 33 per block, the eight blocks a wave then
+            // touches read them from different banks
+            const int cc = q & 31, cr = q >> 5;
+            const int lcx = ilog2((uint32_t)ncx), lcy = lcpb - lcx;
+            g = ((cr >> lcy) << lbpb) | (cc >> lcx);
+            c = ((cr & ((1 << lcy) - 1)) << lcx) | (cc & (ncx - 1));
+        } else {
+            g = q >> lcpb;
+            c = q & ((1 << lcpb) - 1);
+        }
         const bool live = g < G;
         cid[j] = (uint32_t)c;
         bidj[j] = (uint32_t)block_id(live ? g : 0);
@@ -370,7 +386,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         mkj[j] = live ? mk : 0u;
         gbase[j] = live ? tile_base(g) : 0u;
         gj[j] = live ? (uint32_t)g : 0u;
-        opreg[j] = opk[(live ? g : 0) * 32 + (tid & 31)];
+        opreg[j] = opk[(live ? g : 0) * kOpkStride + (tid & 31)];
     }
     const uint32_t fixed_tbl = (a.Tp != 0 ? (1u << 24) : 0u) | (a.Tq != 0 ? (1u << 3) : 0u);
     (void)fixed_tbl;
@@ -399,7 +415,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         uint32_t opv[kCpt];
         if (!kUni) {
 #pragma unroll
-            for (int j = 0; j < kCpt; ++j) opv[j] = opk[gj[j] << 5];
+            for (int j = 0; j < kCpt; ++j) opv[j] = opk[gj[j] * kOpkStride];
         }
         for (int gs = 0; gs < kSteps / 8; ++gs) {
             Ctr4 nxt[kCpt];
@@ -460,7 +476,7 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                     sv[j] = smem[off[j] + kPitch];
                     // behind the site read of a pair's second step: the next
                     // pair's origin word (the last pair reads its own again)
-                    if (!kUni && (e & 1) == 1) opv[j] = opk[(gj[j] << 5) + min((k >> 1) + 1, kSteps / 2 - 1)];
+                    if (!kUni && (e & 1) == 1) opv[j] = opk[gj[j] * kOpkStride + min((k >> 1) + 1, kSteps / 2 - 1)];
                 }
                 // While the reads are in flight: this step's share of the next
                 // Philox call, pinned here so that it is not sunk to its use.
