@@ -124,7 +124,7 @@ __device__ __forceinline__ void run_group(const SweepLaunch &a, int b0, int G, u
     uint32_t *opk = reinterpret_cast<uint32_t *>(smem + core::tile_bytes(a.Bx, a.By, G));
     if (a.Bx == core::kMaxB && a.By == core::kMaxB)
         core::sweep_group<kThreads, kMode, core::kMaxB, true>(a, b0, 1, smem, opk);
-    else if (a.Bx * a.By >= 64 * 64)  // a wave's cells share a block
+    else if (a.Bx * a.By >= 128 * 128)  // a wave's cells share a block
         core::sweep_group<kThreads, kMode, 0, true, false>(a, b0, G, smem, opk);
     else
         core::sweep_group<kThreads, kMode, 0, true, true>(a, b0, G, smem, opk);

@@ -60,8 +60,9 @@ template <int kThreads, int kMode>
 hipError_t launch_m(const SweepLaunch &a, hipStream_t st)
 {
     if (a.Bx == core::kMaxB && a.By == core::kMaxB) return launch_b<kThreads, kMode, core::kMaxB, false>(a, st);
-    // blocks of 64 cells or more: a wave's cells share a block
-    if (a.Bx * a.By >= 64 * 64) return launch_b<kThreads, kMode, 0, false>(a, st);
+    // blocks of 256 cells or more: a wave's cells share a block; smaller ones
+    // spread a wave over a whole tile row (per-lane origins)
+    if (a.Bx * a.By >= 128 * 128) return launch_b<kThreads, kMode, 0, false>(a, st);
     return launch_b<kThreads, kMode, 0, true>(a, st);
 }
 

@@ -211,9 +211,11 @@ __device__ __forceinline__ uint32_t origin_yx(uint32_t w, int odd)
 //   kFixedB = 0:   block sides 32..256 (powers of two), geometry from `a`.
 // Either way the three LDS addresses of an attempt are one register plus
 // offsets (the tile layout above).
-// kLaneOrg (kFixedB = 0 only): blocks of fewer than 64 cells, so that a
-// wave spans several blocks and each lane fetches its block's origins;
-// otherwise a wave's 64 cells share a block (Bx By >= 4096).
+// kLaneOrg (kFixedB = 0 only): the group's cells are numbered as in one
+// 256 x 256 block, so that a wave spans several blocks along a whole tile
+// row and each lane fetches its block's origins (the launches use it below
+// 128 x 128 sites per block); otherwise the cells of a block are consecutive
+// and a wave's 64 cells share a block (needs Bx By >= 4096).
 // smem: at least tile_bytes(Bx, By, G) bytes; opk: G * 36 words of LDS
 // (origins, then the blocks' placement when kFixedB = 0).
 // kStoreThrough: write the new lattice with system-scope stores, which go
@@ -363,12 +365,12 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
         const int q = tid + j * kThreads;
         int g, c;
         if (kLaneOrg) {
-            // blocks under 64 cells: cell q at column q mod 32 and row q / 32
-            // of the tile's 32 x 32 cells, as in one 256 x 256 block, so that
-            // a wave's 64 cells span a whole tile row (all LDS banks) instead
-            // of four neighbouring blocks (half the banks); with the origin
-            // words padded to 33 per block, the eight blocks a wave then
-            // touches read them from different banks
+            // cell q at column q mod 32 and row q / 32 of the tile's 32 x 32
+            // cells, as in one 256 x 256 block, so that a wave's 64 cells span
+            // a whole tile row (all LDS banks) instead of a few neighbouring
+            // blocks (fewer banks); with the origin words padded to 33 per
+            // block, the blocks a wave then touches read them from different
+            // banks
             const int cc = q & 31, cr = q >> 5;
             const int lcx = ilog2((uint32_t)ncx), lcy = lcpb - lcx;
             g = ((cr >> lcy) << lbpb) | (cc >> lcx);
