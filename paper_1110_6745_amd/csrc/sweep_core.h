@@ -526,8 +526,11 @@ __device__ __forceinline__ void sweep_group(SweepLaunch a, const int b0, const i
                             if (phs[j] != (uint32_t)ph) continue;
                             const uint32_t s0 = sv[j];
                             if (s0 != 0u && (kMode == kGrowth || s0 != 0x1Bu)) continue;
-                            const uint32_t l0 = smem[off[j] + kPitch - 1];
-                            const uint32_t d0 = smem[off[j]];
+                            uint32_t l0 = smem[off[j] + kPitch - 1];
+                            uint32_t d0 = smem[off[j]];
+                            // the loads zero-extend; as in the dead-border steps,
+                            // keep the code generator from re-masking the bytes
+                            asm volatile("" : "+v"(l0), "+v"(d0));
                             const uint32_t r = kDrawAccept ? aw[j][e & 3] : 0u;
                             if (!move_accepted<kMode>(s0, l0, d0, fixed_tbl, r, a.Tp, a.Tq)) continue;
                             if (ph == 1) {
