@@ -507,9 +507,14 @@ def main():
                    "lattice_copies": 1 if args.in_place else 2},
         "sweep_kernel_ms": sweep_ms,
         "sweep_site_updates_per_s": N / (sweep_ms * 1e-3),
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
-        "alu_ceiling": alu,
+        # the sweep is bound by VALU issue, not HBM (8.5 % of it): with its
+        # instruction count measured for these sources, the roofline is the
+        # ALU one; the HBM fraction is kept beside it
+        "roofline": ({**alu, "traffic": traffic} if alu else
+                     {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic}),
+        "roofline_hbm": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic},
         "w2_last": w2[-1] if w2 else None,
     }
     if args.psd_calls > 0 and L & (L - 1) == 0:
@@ -524,7 +529,7 @@ def main():
     log(f"sweep leg: {sweep_ms:.3f} ms per MCS, {value:.4g} site updates/s")
     metric_row("sweep", {"L": L, "steps": args.steps, "ms_per_step": out["ms_per_step"],
                          "sweep_kernel_ms": sweep_ms, "site_updates_per_s": value,
-                         "hbm_frac": out["roofline"]["frac"], "width_samples": len(widths)})
+                         "hbm_frac": out["roofline_hbm"]["frac"], "width_samples": len(widths)})
     if not args.no_cpu_baseline and args.cell_borders == "dead":
         out["cpu_baseline"] = cpu_baseline(okpz, sim, seed, p, q)
         log("cpu baseline done")
