@@ -281,9 +281,13 @@ __global__ __launch_bounds__(kThreads, kThreads / 128) void batch_kernel(const J
         // descriptor and state be fetched with scalar loads into SGPRs
         const int r = __builtin_amdgcn_readfirstlane(s_job);
         const uint64_t w = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)s_claim);
-        __syncthreads();
         if (r == -1) break;
-        if (r == -2) continue;
+        if (r == -2) {
+            __syncthreads();  // every thread has read s_job before the next claim rewrites it
+            continue;
+        }
+        // (with an item, the group's own barriers separate these reads from the
+        // next claim)
 
         const int item = (int)(uint32_t)w;
         const JobDesc jd = jobs[r];
