@@ -200,22 +200,6 @@ def test_large_and_small_lattices_in_one_launch(okpz):
     b.free()
 
 
-def paper_sampling_times(t_max, m):
-    """ceil of t_(i+1) = (t_i + 10) e^m from t_0 = 0 (Sec. III), then t_max."""
-    import math
-
-    out, t = [], 0.0
-    while True:
-        t = (t + 10.0) * math.exp(m)
-        if t > t_max:
-            break
-        out.append(math.ceil(t))
-    out = sorted(set(out))
-    if t_max > 0 and (not out or out[-1] != t_max):
-        out.append(t_max)
-    return out
-
-
 def test_steady_state_statistics_match_oracle(okpz):
     # cumulants (Eq. (cumulants)) and Psi_L of the batch's samples against
     # the oracle's exact statistics of its own runs of the same realizations
@@ -226,7 +210,7 @@ def test_steady_state_statistics_match_oracle(okpz):
     jobs = [(L, L, p, q, s0 + r, t_max) for (L, p, q, s0) in groups for r in range(R)]
     b = okpz.Batch(jobs, m)
     b.run()
-    times = [t for t in paper_sampling_times(t_max, m) if t >= t_from]
+    times = [t for t in oracle.sampling_times(t_max, m) if t >= t_from]
     for L, p, q, s0 in groups:
         ens = oracle.ensemble(L, L, p, q, s0, R, t_max)  # S1, S2 after MCS 1..t_max
         vals = [stats.w2_exact(int(ens[r, t - 1, 0]), int(ens[r, t - 1, 1]), L * L)
