@@ -63,7 +63,7 @@ def build(verbose=False):
         r = subprocess.run(cmd, capture_output=True, text=True)
         # pass the compiler's output on, without the resource remarks
         rest = "\n".join(l for l in r.stderr.splitlines()
-                         if "kernel-resource-usage" not in l and not l.startswith(("   ", "      |")))
+                         if "kernel-resource-usage" not in l and not re.match(r"\s*\d*\s*\|", l))
         if rest.strip():
             print(rest, file=sys.stderr, flush=True)
         if r.stdout.strip():
