@@ -58,3 +58,26 @@ def test_sweep_kernels_do_not_spill(kernels):
     assert sweeps
     for n, r in sweeps.items():
         assert r["scratch"] == 0, (n, r)
+
+
+def test_remark_parser():
+    # the compiler's remark lines, as build() reads them
+    from paper_1110_6745_amd.build import parse_resources
+
+    text = "\n".join([
+        "x.hip:20:1: remark: Function Name: _Z1kv [-Rpass-analysis=kernel-resource-usage]",
+        "   20 | {",
+        "      | ^",
+        "x.hip:20:1: remark:     TotalSGPRs: 56 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:20:1: remark:     VGPRs: 30 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:20:1: remark:     AGPRs: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:20:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:20:1: remark:     Occupancy [waves/SIMD]: 8 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:20:1: remark:     LDS Size [bytes/block]: 65920 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark: Function Name: _Z2k2v [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     TotalSGPRs: 91 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    got = parse_resources(text)
+    assert got == {"_Z1kv": {"sgpr": 56, "vgpr": 30, "agpr": 0, "scratch": 0, "occupancy": 8,
+                             "lds": 65920},
+                   "_Z2k2v": {"sgpr": 91}}
