@@ -4,11 +4,10 @@ The library's 1024-thread kernels are meant to run two workgroups per CU
 (16 waves each, 8 per SIMD), which needs at most 64 VGPRs per lane, two LDS
 tiles per CU and few enough scalar registers.  The compiler's occupancy
 figure is not enough for the last: on the MI355X a persistent 1024-thread
-sweep at 95 scalar registers (occupancy 8 by the compiler's count) got one
-workgroup per CU at a time (per-workgroup start clocks: the second started
-when the first ended), while the same kernel capped at 78 ran two at once.
-So every 1024-thread kernel stays at or below 78, the largest count measured
-to fit.  The counts come from the compiler's kernel-resource-usage remarks,
+sweep at 84, 88 or 95 scalar registers (occupancy 8 by the compiler's count)
+got one workgroup per CU at a time (per-workgroup start clocks: the second
+started when the first ended), while the same kernel capped at 62, 78 or 80
+ran two at once.  So every 1024-thread kernel stays at or below 80.  The counts come from the compiler's kernel-resource-usage remarks,
 which build() keeps in paper_1110_6745_amd/_build/kernel_resources.json.
 """
 import json
@@ -47,7 +46,7 @@ def test_1024_thread_kernels_fit_two_workgroups_per_cu(kernels):
     big = {n: r for n, r in kernels.items() if threads_of(n) == 1024}
     assert len(big) >= 36 + 4
     for n, r in big.items():
-        assert r["sgpr"] <= 78, (n, r)
+        assert r["sgpr"] <= 80, (n, r)
         assert r["vgpr"] + r["agpr"] <= 64, (n, r)
         assert 2 * r["lds"] <= LDS_PER_CU, (n, r)
         assert r["occupancy"] >= 8, (n, r)
